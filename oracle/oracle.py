@@ -1,0 +1,239 @@
+"""ctypes front end of the C oracle (test infrastructure only).
+
+All arrays are numpy, C-contiguous.  Functions raise ``OracleError`` with the
+C status code on failure.  Citations refer to sections and equations of the
+paper; the arithmetic itself lives in ``orbf_oracle.c``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborbf_oracle.so")
+
+OK, EINVAL, EDUPLICATE, ESINGULAR = 0, 1, 2, 3
+OP_LAPLACIAN, OP_NEUMANN = 0, 1
+_NAMES = {EINVAL: "EINVAL", EDUPLICATE: "EDUPLICATE", ESINGULAR: "ESINGULAR"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"oracle {what}: {_NAMES.get(code, code)}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = ctypes.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+
+def _declare(L):
+    L.orc_num_monomials.argtypes = [_I, _I]
+    L.orc_num_monomials.restype = _I
+    L.orc_degree_rule.argtypes = [_I, _I, _P, _P]
+    L.orc_degree_rule.restype = None
+    for f in (L.orc_knn_brute, L.orc_knn_grid):
+        f.argtypes = [_P, _I64, _I, _I, _P, _P]
+        f.restype = _I
+    L.orc_knn_one.argtypes = [_P, _I64, _I, _I, _I64, _P, _P]
+    L.orc_knn_one.restype = _I
+    L.orc_cover.argtypes = [_P, _I64, _I, _I, _P, _P, _D, _P, _P, _P, _P]
+    L.orc_cover.restype = _I
+    L.orc_stencil_weights.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _P, _P]
+    L.orc_stencil_weights.restype = _I
+    L.orc_overlapped_rows.argtypes = [_P, _I64, _I, _I, _I, _I, _P, _P, _D,
+                                      _D, _P, _P, _P, _P, _P, _P, _P, _I]
+    L.orc_overlapped_rows.restype = _I
+    L.orc_center_rows.argtypes = [_P, _I64, _I, _I, _I, _I, _I, _P, _I64, _P,
+                                  _P, _P, _P, _I]
+    L.orc_center_rows.restype = _I
+    L.orc_csr.argtypes = [_I64, _I, _P, _P, _P, _P, _P, _P]
+    L.orc_csr.restype = _I
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _check(code, what):
+    if code != OK:
+        raise OracleError(code, what)
+
+
+def num_monomials(d, l):
+    """M = C(l+d, d), the size of the polynomial space (Sec. 2)."""
+    return lib().orc_num_monomials(d, l)
+
+
+def degree_rule(d, n):
+    """Degree s and monomial count M for stencil size n (Sec. 2)."""
+    s = ctypes.c_int()
+    M = ctypes.c_int()
+    lib().orc_degree_rule(d, n, ctypes.byref(s), ctypes.byref(M))
+    return s.value, M.value
+
+
+def knn(x, n, method="auto"):
+    """Stencils I^k (n nearest nodes, self first, ties by index) and rho_k^2.
+
+    Sec. 2 / Sec. 4.1.  ``method``: 'brute', 'grid' or 'auto' (brute force up
+    to 20000 nodes)."""
+    x = _f64(x)
+    N, d = x.shape
+    out = np.empty((N, n), np.int32)
+    rho2 = np.empty(N, np.float64)
+    if method == "auto":
+        method = "brute" if N <= 20000 else "grid"
+    f = lib().orc_knn_brute if method == "brute" else lib().orc_knn_grid
+    _check(f(_ptr(x), N, d, n, _ptr(out), _ptr(rho2)), "knn")
+    return out, rho2
+
+
+def knn_one(x, n, q):
+    """Brute-force stencil of a single node q (sampled checks)."""
+    x = _f64(x)
+    N, d = x.shape
+    out = np.empty(n, np.int32)
+    r = ctypes.c_double()
+    _check(lib().orc_knn_one(_ptr(x), N, d, n, int(q), _ptr(out),
+                             ctypes.byref(r)), "knn_one")
+    return out, r.value
+
+
+def cover(x, knn_idx, rho2, delta, eligible=None):
+    """Greedy overlapped covering without Lebesgue rejection (Sec. 4.1).
+
+    Returns (owner[N], centers[N_delta])."""
+    x = _f64(x)
+    N, d = x.shape
+    n = knn_idx.shape[1]
+    knn_idx = _i32(knn_idx)
+    rho2 = _f64(rho2)
+    el = None if eligible is None else np.ascontiguousarray(eligible, np.uint8)
+    owner = np.empty(N, np.int32)
+    centers = np.empty(N, np.int32)
+    nc = ctypes.c_int64()
+    _check(lib().orc_cover(_ptr(x), N, d, n, _ptr(knn_idx), _ptr(rho2),
+                           float(delta), _ptr(el), _ptr(owner), _ptr(centers),
+                           ctypes.byref(nc)), "cover")
+    return owner, centers[: nc.value].copy()
+
+
+def stencil_weights(P, E, m, l, op=OP_LAPLACIAN, normals=None):
+    """Weights of one stencil P (P[0] the center) at points E.
+
+    Eqs. rbffd_linsys / orbffd_eq / orbffd_rhs (Sec. 4.1); returns
+    W[ne, n], W[e, j] = weight of node j for point e, physical units."""
+    P = _f64(P)
+    E = _f64(np.atleast_2d(E))
+    n, d = P.shape
+    ne = E.shape[0]
+    nr = None if normals is None else _f64(np.atleast_2d(normals))
+    W = np.empty((ne, n), np.float64)
+    _check(lib().orc_stencil_weights(d, m, l, op, n, _ptr(P), ne, _ptr(E),
+                                     _ptr(nr), _ptr(W)), "stencil_weights")
+    return W
+
+
+def overlapped_rows(x, knn_idx, rho2, m, l, delta, tau=np.inf, eligible=None,
+                    nthreads=0):
+    """Laplacian DM rows with the greedy covering and, for finite tau, the
+    L-Lebesgue acceptance test (Sec. 4.1, Sec. 4.2.1).
+
+    Returns dict(owner, centers, W[N,n] (rows aligned with knn[owner]),
+    lam[N], min_margin)."""
+    x = _f64(x)
+    N, d = x.shape
+    n = knn_idx.shape[1]
+    knn_idx = _i32(knn_idx)
+    rho2 = _f64(rho2)
+    el = None if eligible is None else np.ascontiguousarray(eligible, np.uint8)
+    owner = np.empty(N, np.int32)
+    centers = np.empty(N, np.int32)
+    nc = ctypes.c_int64()
+    W = np.zeros((N, n), np.float64)
+    lam = np.zeros(N, np.float64)
+    mm = ctypes.c_double()
+    _check(lib().orc_overlapped_rows(_ptr(x), N, d, n, m, l, _ptr(knn_idx),
+                                     _ptr(rho2), float(delta), float(tau),
+                                     _ptr(el), _ptr(owner), _ptr(centers),
+                                     ctypes.byref(nc), _ptr(W), _ptr(lam),
+                                     ctypes.byref(mm), int(nthreads)),
+           "overlapped_rows")
+    return dict(owner=owner, centers=centers[: nc.value].copy(), W=W, lam=lam,
+                min_margin=mm.value)
+
+
+def center_rows(x, knn_idx, m, l, rows, op=OP_LAPLACIAN, normals=None,
+                owner=None, W=None, nthreads=0):
+    """delta = 1 rows of the listed nodes, each on its own stencil (boundary
+    pass of Sec. 5).  Updates (or creates) owner and W in place."""
+    x = _f64(x)
+    N, d = x.shape
+    n = knn_idx.shape[1]
+    knn_idx = _i32(knn_idx)
+    rows = _i32(rows)
+    if owner is None:
+        owner = np.full(N, -1, np.int32)
+    if W is None:
+        W = np.zeros((N, n), np.float64)
+    nr = None if normals is None else _f64(normals)
+    _check(lib().orc_center_rows(_ptr(x), N, d, n, m, l, op, _ptr(knn_idx),
+                                 len(rows), _ptr(rows), _ptr(nr), _ptr(owner),
+                                 _ptr(W), int(nthreads)), "center_rows")
+    return owner, W
+
+
+def csr(knn_idx, owner, W):
+    """CSR of the DM, columns ascending in each row (Sec. 4.1 scatter)."""
+    N, n = knn_idx.shape
+    knn_idx = _i32(knn_idx)
+    owner = _i32(owner)
+    W = _f64(W)
+    row_ptr = np.empty(N + 1, np.int64)
+    col = np.empty(N * n, np.int32)
+    val = np.empty(N * n, np.float64)
+    _check(lib().orc_csr(N, n, _ptr(knn_idx), _ptr(owner), _ptr(W),
+                         _ptr(row_ptr), _ptr(col), _ptr(val)), "csr")
+    nnz = int(row_ptr[-1])
+    return row_ptr, col[:nnz].copy(), val[:nnz].copy()
+
+
+def build_dm(x, n, m, l, delta, tau=np.inf, eligible=None, boundary=None,
+             normals=None, nthreads=0, knn_method="auto"):
+    """Whole oracle pipeline: stencils, covering (+Lebesgue), interior
+    Laplacian rows, optional normal-derivative rows at ``boundary`` nodes,
+    CSR.  Returns a dict with every intermediate."""
+    idx, rho2 = knn(x, n, knn_method)
+    r = overlapped_rows(x, idx, rho2, m, l, delta, tau, eligible, nthreads)
+    owner, W = r["owner"], r["W"]
+    if boundary is not None and len(boundary):
+        center_rows(x, idx, m, l, boundary, OP_NEUMANN, normals, owner, W,
+                    nthreads)
+    row_ptr, col, val = csr(idx, owner, W)
+    r.update(knn=idx, rho2=rho2, row_ptr=row_ptr, col=col, val=val)
+    return r

@@ -1,0 +1,46 @@
+"""Seeded input generators: determinism, sizes, no coincident nodes."""
+import numpy as np
+
+import nodesets
+
+
+def test_square_grid():
+    a = nodesets.square(45, 0)
+    assert a.shape == (2025, 2)
+    assert np.array_equal(a, nodesets.square(45, 0))
+    h = 1 / 45
+    base_i = (np.arange(2025) % 45 + 0.5) * h
+    assert np.abs(a[:, 0] - base_i).max() <= 0.25 * h
+
+
+def test_disk():
+    D = nodesets.disk(5000, 200, 1)
+    x = D["x"]
+    assert x.shape == (5200, 2) and D["eligible"].sum() == 5000
+    assert np.array_equal(x, nodesets.disk(5000, 200, 1)["x"])
+    r = np.linalg.norm(x, axis=1)
+    assert (r[:5000] <= 1 - 0.5 * 2 * np.pi / 200 + 1e-12).all()
+    assert np.allclose(r[5000:], 1.0)
+    assert np.allclose(np.linalg.norm(D["normals"], axis=1), 1.0)
+    assert len(np.unique(x, axis=0)) == len(x)
+
+
+def test_ball():
+    B = nodesets.ball(20000, 2)
+    x = B["x"]
+    assert x.shape == (20000, 3)
+    assert np.array_equal(x, nodesets.ball(20000, 2)["x"])
+    r = np.linalg.norm(x, axis=1)
+    assert (r <= 1 + 1e-12).all() and np.allclose(r[-B["n_bnd"]:], 1.0)
+    assert len(np.unique(x, axis=0)) == len(x)
+
+
+def test_batch_and_request_specs():
+    s = nodesets.batch_specs()
+    assert len(s) == 512
+    for t in s:
+        assert 2 * t["M"] + 1 <= t["n"] <= 3 * t["M"]
+        assert t["delta"] in (0.2, 0.5, 1.0)
+    r = nodesets.request_specs(100, 10.0)
+    assert all(5e3 - 200 <= q["N"] <= 5e5 + 2000 for q in r)
+    assert all(b["t"] > a["t"] for a, b in zip(r, r[1:]))
