@@ -1,0 +1,203 @@
+/*
+ * orbf.h -- C ABI of liborbf, an MI355X (gfx950) builder of overlapped
+ * RBF-FD differentiation matrices (V. Shankar, "The Overlapped Radial Basis
+ * Function-Finite Difference (RBF-FD) Method: A Generalization of RBF-FD").
+ *
+ * The build has four stream-ordered stages, each an entry point below:
+ *   1. orbf_build_nodes_knn            stencils: each node and its n-1
+ *                                      nearest neighbours (Sec. 2, Sec. 4.1)
+ *   2. orbf_select_overlapped_stencils greedy choice of stencil centers and
+ *                                      of the retention ball rows each one
+ *                                      computes (Sec. 4.1)
+ *   3. orbf_compute_weights            per-center augmented polyharmonic
+ *                                      spline saddle solve with one right-hand
+ *                                      side per retained node (eqs.
+ *                                      rbffd_linsys, orbffd_eq, orbffd_rhs),
+ *                                      optional L-Lebesgue rejection
+ *                                      (Sec. 4.2.1, eq. calLstab)
+ *   4. orbf_assemble_csr               scatter of the weights into the sparse
+ *                                      DM, L(R_i, I_j) = W_{j,i} (Sec. 4.1)
+ *
+ * Conventions for every entry point:
+ *   - Pointers to arrays are DEVICE pointers on the context's device unless
+ *     a comment says "host".  The caller allocates every input and output
+ *     and keeps ownership; the library never frees caller memory.
+ *   - Node coordinates are FP64, array-of-structures: xyz[i*d + a], d = 2|3.
+ *   - All work is enqueued on the context's HIP stream and is asynchronous:
+ *     outputs are valid once the stream (or orbf_sync) has completed.
+ *   - Host-side argument errors return at once and enqueue nothing.
+ *     Errors found on the device (coincident nodes, a singular local system)
+ *     are recorded in a device status word and returned by the next
+ *     orbf_sync; orbf_last_error then names the offending node or stencil.
+ *   - No C++ exception crosses this interface.  A context is used by one
+ *     host thread at a time.
+ */
+#ifndef ORBF_H
+#define ORBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum orbf_status {
+  ORBF_OK = 0,
+  ORBF_EINVAL = 1,     /* invalid argument: d not 2|3, n > N, n < M, even or
+                          too small PHS exponent, delta outside [0,1], tau < 1,
+                          NULL pointer, unsupported size                     */
+  ORBF_EDUPLICATE = 2, /* two distinct nodes at squared distance zero         */
+  ORBF_ESINGULAR = 3,  /* a local saddle system had an exact zero pivot       */
+  ORBF_ENOMEM = 4,     /* device allocation of context scratch failed         */
+  ORBF_EBUDGET = 5,    /* scratch would exceed the context's HBM budget       */
+  ORBF_EHIP = 6,       /* a HIP runtime call failed                           */
+  ORBF_EINTERNAL = 7   /* an internal limit was hit (message says which)      */
+} orbf_status;
+
+typedef enum orbf_op {
+  ORBF_OP_LAPLACIAN = 0, /* L = Laplacian (interior rows, Sec. 4.1 / Sec. 7)  */
+  ORBF_OP_NEUMANN = 1    /* L = n . grad, the normal derivative of the
+                            Neumann boundary operator (Sec. 5)               */
+} orbf_op;
+
+typedef enum orbf_prec {
+  ORBF_PREC_FP64 = 0,   /* factor and solve in FP64                          */
+  ORBF_PREC_FP32_IR = 1 /* factor and solve in FP32, residuals and the
+                           Lebesgue test in FP64, iterative refinement with a
+                           per-stencil FP64 fallback                          */
+} orbf_prec;
+
+typedef struct orbf_ctx orbf_ctx;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  `hbm_budget_bytes` caps the
+ * scratch memory the context may hold (0 = no cap).  *out receives the
+ * context.  Returns ORBF_EHIP if the device cannot be selected. */
+orbf_status orbf_create(int device, void* hip_stream, size_t hbm_budget_bytes,
+                        orbf_ctx** out);
+
+/* Free the context and its scratch (waits for its stream first). */
+void orbf_destroy(orbf_ctx* ctx);
+
+/* Message of the last error on this context ("" if none).  The string is
+ * owned by the context and valid until the next call on it. */
+const char* orbf_last_error(const orbf_ctx* ctx);
+
+/* Wait for the context's stream, then return (and clear) the first error the
+ * device recorded since the previous orbf_sync. */
+orbf_status orbf_sync(orbf_ctx* ctx);
+
+/* Bytes of context scratch one build of N nodes needs (dimension d, stencil
+ * size n, polynomial degree l): what admission control reserves per
+ * request. */
+size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec);
+
+/* Stencils (Sec. 2; Sec. 4.1 with I^k_1 = k).
+ * For every node i, the n nodes nearest to it, itself included, ordered by
+ * the key (squared distance, global index) ascending, so knn[i*n] == i.
+ * Squared distances are ((dx*dx)+(dy*dy))+(dz*dz) in FP64 with every
+ * operation rounded separately; ties are broken by the smaller index.
+ *   xyz  : N*d   FP64 input
+ *   knn  : N*n   int32 output
+ *   rho2 : N     FP64 output, squared stencil width rho_k^2 = squared
+ *                distance to the n-th neighbour (Sec. 4.1)
+ * Errors: EINVAL (d, n < 1, n > N, N > 2^31-1, NULL), EDUPLICATE at sync
+ * time if two nodes coincide. */
+orbf_status orbf_build_nodes_knn(orbf_ctx* ctx, const double* xyz, int64_t N,
+                                 int d, int n, int32_t* knn, double* rho2);
+
+/* Greedy overlapped covering (Sec. 4.1), without Lebesgue rejection.
+ * Nodes are visited in ascending index.  An eligible node not yet claimed
+ * becomes a center k and claims every eligible, unclaimed node j of its
+ * stencil inside the closed retention ball
+ *     d^2(x_k, x_j) <= ((1-delta)*(1-delta)) * rho2[k]
+ * (retention distance (1-delta) rho_k; delta = 1 gives standard RBF-FD with
+ * every eligible node its own center, delta = 0 keeps the whole stencil).
+ * The result is the sequential greedy result exactly, although the device
+ * evaluates it in parallel rounds.
+ *   eligible  : N uint8 (nonzero = gets an interior row) or NULL for all
+ *   centers   : capacity N int32 output, centers in ascending order
+ *   n_centers : 1 int64 output (device): number of centers N_delta
+ *   owner     : N int32 output: center whose stencil computes row j, -1 for
+ *               ineligible nodes (owner[k] == k for centers)
+ *   p         : capacity N int32 output: p[c] = rows computed by centers[c]
+ * Errors: EINVAL (delta outside [0,1] or NaN, sizes, NULL). */
+orbf_status orbf_select_overlapped_stencils(
+    orbf_ctx* ctx, const double* xyz, const int32_t* knn, const double* rho2,
+    int64_t N, int d, int n, double delta, const uint8_t* eligible,
+    int32_t* centers, int64_t* n_centers, int32_t* owner, int32_t* p);
+
+/* Arguments of orbf_compute_weights beyond the operator description. */
+typedef struct orbf_weights_args {
+  const double* xyz;     /* N*d nodes                                        */
+  int64_t N;             /* number of nodes                                  */
+  int d;                 /* dimension, 2 or 3                                */
+  const int32_t* knn;    /* N*n stencils from orbf_build_nodes_knn           */
+  const double* rho2;    /* N squared stencil widths                         */
+  /* Row selection, one of three modes:
+   *  (a) rows != NULL: explicit rows; row rows[i] is computed at its own node
+   *      on its own stencil (delta = 1), e.g. the boundary rows of Sec. 5;
+   *      owner[rows[i]] is set to rows[i].
+   *  (b) rows == NULL, tau infinite: the covering of
+   *      orbf_select_overlapped_stencils; `centers`, `n_centers` and `owner`
+   *      are its outputs, read here.
+   *  (c) rows == NULL, tau finite: the covering is recomputed with the
+   *      L-Lebesgue rejection of Sec. 4.2.1 and `centers`, `n_centers`,
+   *      `owner` are OUTPUTS (capacities N). */
+  const int32_t* rows;   /* n_rows explicit row nodes, or NULL               */
+  int64_t n_rows;        /* number of explicit rows (host value)             */
+  int32_t* centers;      /* see above                                        */
+  int64_t* n_centers;    /* device scalar, see above                         */
+  int32_t* owner;        /* N, see above                                     */
+  const uint8_t* eligible; /* mode (c): nodes that get rows (NULL = all)     */
+  const double* normals; /* n_rows*d unit normals (ORBF_OP_NEUMANN)          */
+  double tau;            /* Lebesgue threshold: node e of stencil k is kept
+                            iff e is the center or
+                            Lambda(x_e) <= tau * Lambda(x_ref), x_ref the
+                            stencil node nearest the stencil centroid; tau = 1
+                            is eq. calLstab; INFINITY disables the test     */
+  orbf_prec prec;        /* ORBF_PREC_FP64 or ORBF_PREC_FP32_IR              */
+  double* W;             /* N*n output: W[e*n + q] is the weight of node
+                            knn[owner[e]*n + q] in row e (physical units)    */
+  double* lebesgue;      /* N output or NULL: Lambda of each computed row    */
+  int32_t* ir_steps;     /* N output or NULL (FP32_IR): refinement steps of
+                            the row's stencil, -1 if it fell back to FP64    */
+} orbf_weights_args;
+
+/* Local weights (Sec. 4.1, eqs. rbffd_linsys, orbffd_eq, orbffd_rhs).
+ * For each center k: scaled coordinates xi = (x - x_k)/rho_k, the
+ * (n+M) x (n+M) system [A Psi; Psi^T 0] with A_ij = |xi_i - xi_j|^m and Psi
+ * the M = C(l+d, d) monomials of degree <= l, one right-hand side per
+ * computed row e holding L|xi - xi_j|^m and L psi at xi_e; partial-pivot LU
+ * and triangular solves; weights unscaled by rho_k^2 (Laplacian) or rho_k
+ * (normal derivative); W^psi is discarded.
+ *   op : ORBF_OP_LAPLACIAN (needs m >= 3) or ORBF_OP_NEUMANN (mode (a) only)
+ *   m  : odd PHS exponent >= 3;  l : polynomial degree >= 0;
+ *   n  : stencil size (>= M);    delta : overlap parameter in [0,1] (mode c)
+ * Errors: EINVAL (parameters, NULL outputs, n + M > 160, mode/op mismatch),
+ * ESINGULAR at sync time (exact zero pivot; the stencil's rows are NaN). */
+orbf_status orbf_compute_weights(orbf_ctx* ctx, orbf_op op, int m, int l,
+                                 int n, double delta,
+                                 const orbf_weights_args* args);
+
+/* Sparse DM in CSR (Sec. 4.1: L(R^k_i, I^k_j) = W^{phi,k}_{j,i}).
+ * Row e holds the n indices of stencil owner[e] in ascending order with the
+ * matching weights of W (row e); rows with owner[e] < 0 are empty.
+ *   row_ptr : N+1 int64 output;  col : N*n int32;  val : N*n FP64 outputs
+ *             (only row_ptr[N] entries are written). */
+orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
+                              const int32_t* knn, const int32_t* owner,
+                              const double* W, int64_t* row_ptr, int32_t* col,
+                              double* val);
+
+/* Phase timing of the most recent calls on this context, in milliseconds of
+ * stream time (HIP events around each entry point's kernels): [0] kNN,
+ * [1] covering, [2] weights, [3] CSR, [4] duration of the weights kernel's
+ * last launch.  Valid after orbf_sync. */
+orbf_status orbf_phase_times(orbf_ctx* ctx, double* ms5 /* host, 5 */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ORBF_H */

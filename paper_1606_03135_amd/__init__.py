@@ -1,0 +1,274 @@
+"""Overlapped RBF-FD differentiation matrices on MI355X (gfx950).
+
+Thin ctypes binding of ``liborbf.so`` (C ABI in ``include/orbf.h``).  Every
+numerical step runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch provides device memory and the current HIP stream.
+
+The functions mirror the ABI:
+
+    build_nodes_knn(ctx, xyz, n)                       -> knn, rho2
+    select_overlapped_stencils(ctx, xyz, knn, rho2, delta, eligible=None)
+                                                       -> centers, n_centers,
+                                                          owner, p
+    compute_weights(ctx, op, m, l, n, delta, xyz, knn, rho2, ...) -> W
+    assemble_csr(ctx, knn, owner, W)                   -> row_ptr, col, val
+
+and ``build_dm`` chains them for a whole node set (Sec. 4.1 of the paper:
+stencils, greedy retention-ball covering, per-stencil saddle solves, CSR;
+optional normal-derivative rows at listed boundary nodes, Sec. 5).
+
+If the library has not been built the import still succeeds, but every call
+raises ``RuntimeError``: there is no CPU fallback.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborbf.so")
+
+OK, EINVAL, EDUPLICATE, ESINGULAR, ENOMEM, EBUDGET, EHIP, EINTERNAL = range(8)
+OP_LAPLACIAN, OP_NEUMANN = 0, 1
+PREC_FP64, PREC_FP32_IR = 0, 1
+STATUS_NAMES = ["OK", "EINVAL", "EDUPLICATE", "ESINGULAR", "ENOMEM",
+                "EBUDGET", "EHIP", "EINTERNAL"]
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+
+class OrbfError(RuntimeError):
+    def __init__(self, code, msg):
+        name = STATUS_NAMES[code] if 0 <= code < len(STATUS_NAMES) else code
+        super().__init__(f"orbf {name}: {msg}")
+        self.code = code
+
+
+class WeightsArgs(ctypes.Structure):
+    _fields_ = [("xyz", _P), ("N", _I64), ("d", _I), ("knn", _P),
+                ("rho2", _P), ("rows", _P), ("n_rows", _I64),
+                ("centers", _P), ("n_centers", _P), ("owner", _P),
+                ("eligible", _P), ("normals", _P), ("tau", _D), ("prec", _I),
+                ("W", _P), ("lebesgue", _P), ("ir_steps", _P)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liborbf (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "liborbf.so is not built; run __graft_entry__.build() or "
+                "python paper_1606_03135_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        L.orbf_create.argtypes = [_I, _P, ctypes.c_size_t, ctypes.c_void_p]
+        L.orbf_create.restype = _I
+        L.orbf_destroy.argtypes = [_P]
+        L.orbf_destroy.restype = None
+        L.orbf_last_error.argtypes = [_P]
+        L.orbf_last_error.restype = ctypes.c_char_p
+        L.orbf_sync.argtypes = [_P]
+        L.orbf_sync.restype = _I
+        L.orbf_workspace_size.argtypes = [_I64, _I, _I, _I, _I]
+        L.orbf_workspace_size.restype = ctypes.c_size_t
+        L.orbf_build_nodes_knn.argtypes = [_P, _P, _I64, _I, _I, _P, _P]
+        L.orbf_build_nodes_knn.restype = _I
+        L.orbf_select_overlapped_stencils.argtypes = [
+            _P, _P, _P, _P, _I64, _I, _I, _D, _P, _P, _P, _P, _P]
+        L.orbf_select_overlapped_stencils.restype = _I
+        L.orbf_compute_weights.argtypes = [_P, _I, _I, _I, _I, _D,
+                                           ctypes.POINTER(WeightsArgs)]
+        L.orbf_compute_weights.restype = _I
+        L.orbf_assemble_csr.argtypes = [_P, _I64, _I, _P, _P, _P, _P, _P, _P]
+        L.orbf_assemble_csr.restype = _I
+        L.orbf_phase_times.argtypes = [_P, ctypes.POINTER(_D)]
+        L.orbf_phase_times.restype = _I
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    return t.contiguous()
+
+
+class Context:
+    """Library context bound to a device and a HIP stream (default: torch's
+    current stream on ``device``).  ``budget`` caps the scratch memory in
+    bytes (0 = no cap)."""
+
+    def __init__(self, device=0, stream=None, budget=0):
+        L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = L.orbf_create(device, ctypes.c_void_p(stream.cuda_stream),
+                           int(budget), ctypes.byref(h))
+        if rc != OK:
+            raise OrbfError(rc, "orbf_create failed")
+        self._h = h
+
+    def check(self, rc):
+        if rc != OK:
+            msg = lib().orbf_last_error(self._h).decode()
+            raise OrbfError(rc, msg)
+
+    def sync(self):
+        """Wait for the stream and raise any error the device recorded."""
+        self.check(lib().orbf_sync(self._h))
+
+    def phase_times(self):
+        """[kNN, covering, weights, CSR, last weights kernel] in ms."""
+        a = (_D * 5)()
+        self.check(lib().orbf_phase_times(self._h, a))
+        return list(a)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().orbf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_size(N, d, n, l, prec=PREC_FP64):
+    return lib().orbf_workspace_size(int(N), int(d), int(n), int(l), int(prec))
+
+
+def build_nodes_knn(ctx, xyz, n):
+    """Stencils (Sec. 2, Sec. 4.1): knn[N, n] int32 (self first), rho2[N]."""
+    xyz = _dev(xyz, torch.float64, "xyz")
+    N, d = xyz.shape
+    knn = torch.empty((N, n), dtype=torch.int32, device=xyz.device)
+    rho2 = torch.empty(N, dtype=torch.float64, device=xyz.device)
+    ctx.check(lib().orbf_build_nodes_knn(ctx._h, _ptr(xyz), N, d, n,
+                                         _ptr(knn), _ptr(rho2)))
+    return knn, rho2
+
+
+def select_overlapped_stencils(ctx, xyz, knn, rho2, delta, eligible=None):
+    """Greedy overlapped covering (Sec. 4.1).  Returns centers (capacity N;
+    the first n_centers entries are valid), n_centers (device int64 scalar
+    tensor), owner[N] and p (rows per center, aligned with centers)."""
+    xyz = _dev(xyz, torch.float64, "xyz")
+    knn = _dev(knn, torch.int32, "knn")
+    rho2 = _dev(rho2, torch.float64, "rho2")
+    N, d = xyz.shape
+    n = knn.shape[1]
+    if eligible is not None:
+        eligible = _dev(eligible, torch.uint8, "eligible")
+    dev = xyz.device
+    centers = torch.empty(N, dtype=torch.int32, device=dev)
+    n_centers = torch.zeros(1, dtype=torch.int64, device=dev)
+    owner = torch.empty(N, dtype=torch.int32, device=dev)
+    p = torch.empty(N, dtype=torch.int32, device=dev)
+    ctx.check(lib().orbf_select_overlapped_stencils(
+        ctx._h, _ptr(xyz), _ptr(knn), _ptr(rho2), N, d, n, float(delta),
+        _ptr(eligible), _ptr(centers), _ptr(n_centers), _ptr(owner), _ptr(p)))
+    return centers, n_centers, owner, p
+
+
+def compute_weights(ctx, op, m, l, n, delta, xyz, knn, rho2, *, centers=None,
+                    n_centers=None, owner=None, rows=None, normals=None,
+                    eligible=None, tau=math.inf, prec=PREC_FP64, W=None,
+                    lebesgue=None, ir_steps=None):
+    """Local weights (Sec. 4.1 eqs. rbffd_linsys / orbffd_eq / orbffd_rhs).
+
+    Rows come from the covering (centers, n_centers, owner) or from an
+    explicit ``rows`` list (each at its own node, delta = 1, e.g. boundary
+    normal-derivative rows with ``normals``).  Returns W[N, n]: row e holds
+    the weights of stencil owner[e] in stencil order."""
+    xyz = _dev(xyz, torch.float64, "xyz")
+    knn = _dev(knn, torch.int32, "knn")
+    rho2 = _dev(rho2, torch.float64, "rho2")
+    N, d = xyz.shape
+    if W is None:
+        W = torch.empty((N, n), dtype=torch.float64, device=xyz.device)
+    a = WeightsArgs()
+    a.xyz, a.N, a.d, a.knn, a.rho2 = _ptr(xyz), N, d, _ptr(knn), _ptr(rho2)
+    if rows is not None:
+        rows = _dev(rows, torch.int32, "rows")
+        a.rows, a.n_rows = _ptr(rows), rows.numel()
+        if owner is not None:
+            a.owner = _ptr(owner)
+    else:
+        a.centers, a.n_centers, a.owner = (_ptr(centers), _ptr(n_centers),
+                                           _ptr(owner))
+    if normals is not None:
+        normals = _dev(normals, torch.float64, "normals")
+        a.normals = _ptr(normals)
+    if eligible is not None:
+        a.eligible = _ptr(_dev(eligible, torch.uint8, "eligible"))
+    a.tau = float(tau)
+    a.prec = int(prec)
+    a.W = _ptr(W)
+    a.lebesgue = _ptr(lebesgue)
+    a.ir_steps = _ptr(ir_steps)
+    ctx.check(lib().orbf_compute_weights(ctx._h, int(op), int(m), int(l),
+                                         int(n), float(delta),
+                                         ctypes.byref(a)))
+    return W
+
+
+def assemble_csr(ctx, knn, owner, W):
+    """CSR of the DM (Sec. 4.1 scatter), columns ascending per row."""
+    knn = _dev(knn, torch.int32, "knn")
+    owner = _dev(owner, torch.int32, "owner")
+    W = _dev(W, torch.float64, "W")
+    N, n = knn.shape
+    dev = knn.device
+    row_ptr = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(N * n, dtype=torch.int32, device=dev)
+    val = torch.empty(N * n, dtype=torch.float64, device=dev)
+    ctx.check(lib().orbf_assemble_csr(ctx._h, N, n, _ptr(knn), _ptr(owner),
+                                      _ptr(W), _ptr(row_ptr), _ptr(col),
+                                      _ptr(val)))
+    return row_ptr, col, val
+
+
+def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
+             boundary=None, normals=None, prec=PREC_FP64, ctx=None,
+             sync=True):
+    """Whole DM build on the device: stencils, covering, interior Laplacian
+    rows, optional normal-derivative rows at ``boundary`` nodes, CSR.
+    Returns a dict of device tensors (plus ``ctx``)."""
+    own_ctx = ctx is None
+    if own_ctx:
+        ctx = Context(xyz.device.index or 0)
+    knn, rho2 = build_nodes_knn(ctx, xyz, n)
+    centers, n_centers, owner, p = select_overlapped_stencils(
+        ctx, xyz, knn, rho2, delta, eligible)
+    lam = torch.zeros(xyz.shape[0], dtype=torch.float64, device=xyz.device)
+    W = compute_weights(ctx, OP_LAPLACIAN, m, l, n, delta, xyz, knn, rho2,
+                        centers=centers, n_centers=n_centers, owner=owner,
+                        eligible=eligible, tau=tau, prec=prec, lebesgue=lam)
+    if boundary is not None and len(boundary):
+        compute_weights(ctx, OP_NEUMANN, m, l, n, 1.0, xyz, knn, rho2,
+                        rows=boundary, normals=normals, owner=owner, W=W,
+                        lebesgue=lam, prec=prec)
+    row_ptr, col, val = assemble_csr(ctx, knn, owner, W)
+    if sync:
+        ctx.sync()
+    return dict(knn=knn, rho2=rho2, centers=centers, n_centers=n_centers,
+                owner=owner, p=p, W=W, lam=lam, row_ptr=row_ptr, col=col,
+                val=val, ctx=ctx)

@@ -1,0 +1,281 @@
+// C ABI of liborbf: contexts, argument checking, scratch management, phase
+// timing and the device status word.  The numerical work is in knn.hip,
+// cover.hip, weights.hip and csr.hip.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "orbf_internal.hpp"
+
+namespace orbf {
+
+orbf_status fail(orbf_ctx* ctx, orbf_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+orbf_status hip_check(orbf_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return ORBF_OK;
+  return fail(ctx, ORBF_EHIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Grow-only scratch buffer `id`.  A larger request frees the old buffer;
+// hipFree waits for the device, so kernels still using it have finished.
+void* scratch(orbf_ctx* ctx, int id, size_t bytes, orbf_status* st) {
+  if (*st != ORBF_OK) return nullptr;
+  Buffer& b = ctx->buf[id];
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return b.ptr;
+  size_t want = bytes + bytes / 8 + 256;
+  if (ctx->budget && ctx->held - b.bytes + want > ctx->budget) {
+    *st = fail(ctx, ORBF_EBUDGET,
+               "scratch of " + std::to_string(want) +
+                   " bytes exceeds the context's HBM budget");
+    return nullptr;
+  }
+  if (b.ptr) {
+    hipFree(b.ptr);
+    ctx->held -= b.bytes;
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  if (hipMalloc(&b.ptr, want) != hipSuccess) {
+    b.ptr = nullptr;
+    *st = fail(ctx, ORBF_ENOMEM, "hipMalloc of " + std::to_string(want) +
+                                     " bytes of scratch failed");
+    return nullptr;
+  }
+  b.bytes = want;
+  ctx->held += want;
+  return b.ptr;
+}
+
+static int num_monomials(int d, int l) {
+  long num = 1, den = 1;
+  for (int i = 1; i <= d; ++i) {
+    num *= (l + i);
+    den *= i;
+  }
+  return (int)(num / den);
+}
+
+}  // namespace orbf
+
+using namespace orbf;
+
+namespace {
+
+const char* status_name(int c) {
+  switch (c) {
+    case ORBF_OK: return "OK";
+    case ORBF_EINVAL: return "EINVAL";
+    case ORBF_EDUPLICATE: return "EDUPLICATE";
+    case ORBF_ESINGULAR: return "ESINGULAR";
+    case ORBF_ENOMEM: return "ENOMEM";
+    case ORBF_EBUDGET: return "EBUDGET";
+    case ORBF_EHIP: return "EHIP";
+    default: return "EINTERNAL";
+  }
+}
+
+orbf_status check_common(orbf_ctx* ctx, int64_t N, int d, int n) {
+  if (!ctx) return ORBF_EINVAL;
+  if (d != 2 && d != 3) return fail(ctx, ORBF_EINVAL, "d must be 2 or 3");
+  if (N < 1 || N > INT32_MAX) return fail(ctx, ORBF_EINVAL, "N out of range");
+  if (n < 1 || n > N) return fail(ctx, ORBF_EINVAL, "need 1 <= n <= N");
+  if (n > 128) return fail(ctx, ORBF_EINVAL, "stencil size n > 128");
+  return ORBF_OK;
+}
+
+struct PhaseTimer {
+  orbf_ctx* ctx;
+  int slot;
+  PhaseTimer(orbf_ctx* c, int s) : ctx(c), slot(s) {
+    hipEventRecord(ctx->ev[2 * s], ctx->stream);
+  }
+  ~PhaseTimer() {
+    hipEventRecord(ctx->ev[2 * slot + 1], ctx->stream);
+    ctx->phase_valid[slot] = true;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+orbf_status orbf_create(int device, void* hip_stream, size_t hbm_budget_bytes,
+                        orbf_ctx** out) {
+  if (!out) return ORBF_EINVAL;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return ORBF_EHIP;
+  orbf_ctx* ctx = new (std::nothrow) orbf_ctx();
+  if (!ctx) return ORBF_ENOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->budget = hbm_budget_bytes;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+    ctx->num_cus = prop.multiProcessorCount;
+  if (hipMalloc(&ctx->status, sizeof(DevStatus)) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->status_host, sizeof(DevStatus),
+                    hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return ORBF_ENOMEM;
+  }
+  hipMemset(ctx->status, 0, sizeof(DevStatus));
+  for (auto& e : ctx->ev) hipEventCreate(&e);
+  *out = ctx;
+  return ORBF_OK;
+}
+
+void orbf_destroy(orbf_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  for (auto& b : ctx->buf)
+    if (b.ptr) hipFree(b.ptr);
+  if (ctx->status) hipFree(ctx->status);
+  if (ctx->status_host) hipHostFree(ctx->status_host);
+  for (auto& e : ctx->ev)
+    if (e) hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* orbf_last_error(const orbf_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "no context";
+}
+
+orbf_status orbf_sync(orbf_ctx* ctx) {
+  if (!ctx) return ORBF_EINVAL;
+  hipSetDevice(ctx->device);
+  hipError_t e = hipMemcpyAsync(ctx->status_host, ctx->status,
+                                sizeof(DevStatus), hipMemcpyDeviceToHost,
+                                ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_check(ctx, e, "sync");
+  const DevStatus s = *ctx->status_host;
+  if (s.code == 0) return ORBF_OK;
+  hipMemsetAsync(ctx->status, 0, sizeof(DevStatus), ctx->stream);
+  hipStreamSynchronize(ctx->stream);
+  char msg[160];
+  snprintf(msg, sizeof msg, "device reported %s at node/stencil %d",
+           status_name(s.code), s.where);
+  ctx->err = msg;
+  return (orbf_status)s.code;
+}
+
+size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
+  (void)l;
+  (void)prec;
+  if (N < 1 || n < 1) return 0;
+  const size_t Nn = (size_t)N;
+  // grid: cell ids, ranks, counts, starts, permutation, sorted coordinates
+  size_t knn = Nn * 4 * 3 + (Nn + 66) * 8 + Nn * 4 + Nn * (size_t)d * 8;
+  // covering: masks, degrees, starts, fill, state, flags, positions, list,
+  // predecessor lists (bounded by N (n-1))
+  size_t cover = Nn * 16 + Nn * 4 * 5 + Nn * 8 * 2 + Nn * (size_t)(n - 1) * 4;
+  size_t scan = (Nn / 1024 + 64) * 16 + 256;
+  return (knn > cover ? knn : cover) + knn / 4 + scan + (1 << 20);
+}
+
+orbf_status orbf_build_nodes_knn(orbf_ctx* ctx, const double* xyz, int64_t N,
+                                 int d, int n, int32_t* knn, double* rho2) {
+  orbf_status st = check_common(ctx, N, d, n);
+  if (st) return st;
+  if (!xyz || !knn || !rho2) return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  hipSetDevice(ctx->device);
+  PhaseTimer t(ctx, 0);
+  return launch_knn(ctx, xyz, N, d, n, knn, rho2);
+}
+
+orbf_status orbf_select_overlapped_stencils(
+    orbf_ctx* ctx, const double* xyz, const int32_t* knn, const double* rho2,
+    int64_t N, int d, int n, double delta, const uint8_t* eligible,
+    int32_t* centers, int64_t* n_centers, int32_t* owner, int32_t* p) {
+  orbf_status st = check_common(ctx, N, d, n);
+  if (st) return st;
+  if (!(delta >= 0.0 && delta <= 1.0))
+    return fail(ctx, ORBF_EINVAL, "delta must lie in [0, 1]");
+  if (!xyz || !knn || !rho2 || !centers || !n_centers || !owner)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  hipSetDevice(ctx->device);
+  const double t = 1.0 - delta;
+  const double t2 = t * t;
+  PhaseTimer tm(ctx, 1);
+  return launch_cover(ctx, xyz, knn, rho2, N, d, n, t2, eligible, centers,
+                      n_centers, owner, p);
+}
+
+orbf_status orbf_compute_weights(orbf_ctx* ctx, orbf_op op, int m, int l,
+                                 int n, double delta,
+                                 const orbf_weights_args* a) {
+  if (!ctx || !a) return ORBF_EINVAL;
+  orbf_status st = check_common(ctx, a->N, a->d, n);
+  if (st) return st;
+  if (op != ORBF_OP_LAPLACIAN && op != ORBF_OP_NEUMANN)
+    return fail(ctx, ORBF_EINVAL, "unknown operator");
+  if (m < 3 || m % 2 == 0)
+    return fail(ctx, ORBF_EINVAL, "PHS exponent m must be odd and >= 3");
+  if (l < 0) return fail(ctx, ORBF_EINVAL, "polynomial degree l < 0");
+  const int M = num_monomials(a->d, l);
+  if (n < M) return fail(ctx, ORBF_EINVAL, "stencil size n < C(l+d, d)");
+  if (n + M > 160) return fail(ctx, ORBF_EINVAL, "n + M > 160");
+  if (!(delta >= 0.0 && delta <= 1.0))
+    return fail(ctx, ORBF_EINVAL, "delta must lie in [0, 1]");
+  if (!(a->tau >= 1.0)) return fail(ctx, ORBF_EINVAL, "tau must be >= 1");
+  if (!a->xyz || !a->knn || !a->rho2 || !a->W)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  if (a->prec != ORBF_PREC_FP64 && a->prec != ORBF_PREC_FP32_IR)
+    return fail(ctx, ORBF_EINVAL, "unknown precision");
+  const bool explicit_rows = a->rows != nullptr;
+  if (explicit_rows) {
+    if (a->n_rows < 0) return fail(ctx, ORBF_EINVAL, "n_rows < 0");
+    if (op == ORBF_OP_NEUMANN && !a->normals)
+      return fail(ctx, ORBF_EINVAL, "NEUMANN rows need normals");
+  } else {
+    if (op != ORBF_OP_LAPLACIAN)
+      return fail(ctx, ORBF_EINVAL,
+                  "covered rows use the Laplacian; list boundary rows explicitly");
+    if (!a->centers || !a->n_centers || !a->owner)
+      return fail(ctx, ORBF_EINVAL, "NULL covering pointer");
+    if (!isinf(a->tau))
+      return fail(ctx, ORBF_EINVAL, "finite tau is not supported yet");
+  }
+  hipSetDevice(ctx->device);
+  const double t = 1.0 - delta;
+  PhaseTimer tm(ctx, 2);
+  return launch_weights(ctx, op, m, l, n, t * t, a);
+}
+
+orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
+                              const int32_t* knn, const int32_t* owner,
+                              const double* W, int64_t* row_ptr, int32_t* col,
+                              double* val) {
+  if (!ctx) return ORBF_EINVAL;
+  if (N < 1 || N > INT32_MAX || n < 1 || n > 128)
+    return fail(ctx, ORBF_EINVAL, "N or n out of range");
+  if (!knn || !owner || !W || !row_ptr || !col || !val)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  hipSetDevice(ctx->device);
+  PhaseTimer tm(ctx, 3);
+  return launch_csr(ctx, N, n, knn, owner, W, row_ptr, col, val);
+}
+
+orbf_status orbf_phase_times(orbf_ctx* ctx, double* ms5) {
+  if (!ctx || !ms5) return ORBF_EINVAL;
+  for (int s = 0; s < 5; ++s) {
+    ms5[s] = -1.0;
+    if (!ctx->phase_valid[s]) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[2 * s], ctx->ev[2 * s + 1]) ==
+        hipSuccess)
+      ms5[s] = ms;
+  }
+  return ORBF_OK;
+}
+
+}  // extern "C"

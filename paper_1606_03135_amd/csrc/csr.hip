@@ -1,0 +1,84 @@
+// Sparse DM in CSR (Sec. 4.1: L(R^k_i, I^k_j) = W^{phi,k}_{j,i}).
+// Row pointers are a prefix sum of the row lengths (n for every row with an
+// owner).  One wavefront per row ranks the n stencil indices of the owner's
+// stencil (all distinct) by a wave-wide comparison and writes each (index,
+// weight) pair at its rank, so every row is written with coalesced stores.
+#include "orbf_internal.hpp"
+
+namespace orbf {
+
+namespace {
+
+__global__ __launch_bounds__(256) void row_len_kernel(
+    const int32_t* __restrict__ owner, int64_t N, int n,
+    int32_t* __restrict__ len) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < N) len[e] = owner[e] >= 0 ? n : 0;
+}
+
+template <int PER_LANE>
+__global__ __launch_bounds__(256) void csr_scatter_kernel(
+    const int32_t* __restrict__ knn, const int32_t* __restrict__ owner,
+    const double* __restrict__ W, int64_t N, int n,
+    const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+    double* __restrict__ val) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < N;
+       e += (int64_t)gridDim.x * 4) {
+    const int32_t o = owner[e];
+    if (o < 0 || o >= N) continue;
+    const int64_t base = row_ptr[e];
+    int32_t idx[PER_LANE];
+    double w[PER_LANE];
+#pragma unroll
+    for (int h = 0; h < PER_LANE; ++h) {
+      const int q = lane + 64 * h;
+      idx[h] = q < n ? knn[(int64_t)o * n + q] : INT32_MAX;
+      w[h] = q < n ? W[e * n + q] : 0.0;
+    }
+    int rank[PER_LANE];
+#pragma unroll
+    for (int h = 0; h < PER_LANE; ++h) rank[h] = 0;
+#pragma unroll
+    for (int g = 0; g < PER_LANE; ++g) {
+      for (int s = 0; s < 64; ++s) {
+        const int32_t v = __shfl(idx[g], s, 64);
+#pragma unroll
+        for (int h = 0; h < PER_LANE; ++h) rank[h] += v < idx[h];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < PER_LANE; ++h) {
+      if (lane + 64 * h < n) {
+        col[base + rank[h]] = idx[h];
+        val[base + rank[h]] = w[h];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
+                       const int32_t* owner, const double* W,
+                       int64_t* row_ptr, int32_t* col, double* val) {
+  orbf_status st = ORBF_OK;
+  auto* len = (int32_t*)scratch(ctx, B_INDEG, (size_t)(N + 1) * 4, &st);
+  if (st) return st;
+  hipStream_t s = ctx->stream;
+  const unsigned g = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL(row_len_kernel, dim3(g), dim3(256), 0, s, owner, N, n, len);
+  st = exclusive_scan_i32_to_i64(ctx, len, N, row_ptr);
+  if (st) return st;
+  const int64_t blocks = (N + 3) / 4;
+  const dim3 grid((unsigned)(blocks < (1 << 20) ? blocks : (1 << 20)));
+  if (n <= 64)
+    hipLaunchKernelGGL(csr_scatter_kernel<1>, grid, dim3(256), 0, s, knn,
+                       owner, W, N, n, row_ptr, col, val);
+  else
+    hipLaunchKernelGGL(csr_scatter_kernel<2>, grid, dim3(256), 0, s, knn,
+                       owner, W, N, n, row_ptr, col, val);
+  return hip_check(ctx, hipGetLastError(), "csr");
+}
+
+}  // namespace orbf

@@ -1,0 +1,124 @@
+// Internal declarations of liborbf (HIP, gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "orbf.h"
+
+namespace orbf {
+
+// Device status word: [0] = first error code (0 = none), [1] = the node or
+// stencil it concerns.  Written with atomicCAS so the first error wins.
+struct DevStatus {
+  int code;
+  int where;
+};
+
+__device__ __forceinline__ void report(DevStatus* st, int code, int where) {
+  if (atomicCAS(&st->code, 0, code) == 0) atomicExch(&st->where, where);
+}
+
+// Squared distance ((dx*dx)+(dy*dy))+(dz*dz), every operation rounded on its
+// own: stencil order and retention-ball membership are integer decisions
+// taken on these values, and they must be reproducible bit for bit.
+__device__ __forceinline__ double exact_sqdist(double ax, double ay, double az,
+                                               double bx, double by, double bz,
+                                               int d) {
+#pragma clang fp contract(off)
+  double dx = ax - bx;
+  double s = dx * dx;
+  double dy = ay - by;
+  s = s + dy * dy;
+  if (d == 3) {
+    double dz = az - bz;
+    s = s + dz * dz;
+  }
+  return s;
+}
+
+// Uniform bucket grid over the node set (replaces the kd-tree of Sec. 2).
+struct GridParams {
+  double lo[3];
+  double s;      // cell side
+  double inv_s;  // 1/s
+  double diag2;  // squared bounding-box diagonal, with slack
+  int nc[3];     // cells per axis
+  int ncell;     // product of nc
+};
+
+// Scratch buffers owned by a context; grow-only.
+struct Buffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace orbf
+
+struct orbf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t held = 0;
+  std::string err;
+  orbf::DevStatus* status = nullptr;  // device
+  orbf::DevStatus* status_host = nullptr;  // pinned mirror
+  orbf::Buffer buf[24];
+  int num_cus = 256;
+  hipEvent_t ev[10] = {};
+  float phase_ms[5] = {0, 0, 0, 0, 0};
+  bool phase_valid[5] = {false, false, false, false, false};
+  int32_t* host_counter = nullptr;  // pinned, covering round control
+};
+
+namespace orbf {
+
+enum BufId {
+  B_GRID_PARAMS = 0,
+  B_PARTIAL,
+  B_CELL_OF,
+  B_CELL_RANK,
+  B_CELL_START,
+  B_SCAN_TMP,
+  B_PERM,
+  B_XS,
+  B_BALL,
+  B_INDEG,
+  B_PRED_START,
+  B_PRED_FILL,
+  B_PRED,
+  B_STATE,
+  B_FLAGS,
+  B_COUNTER,
+  B_CENTER_POS,
+  B_ROWPTR_TMP,
+  B_W_TMP,
+  B_MISC,
+};
+
+// ctx helpers (api.hip)
+orbf_status fail(orbf_ctx* ctx, orbf_status code, const std::string& msg);
+void* scratch(orbf_ctx* ctx, int id, size_t bytes, orbf_status* st);
+orbf_status hip_check(orbf_ctx* ctx, hipError_t e, const char* what);
+
+// exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total),
+// int64 output; temp from scratch (scan.hip)
+orbf_status exclusive_scan_i32_to_i64(orbf_ctx* ctx, const int32_t* in,
+                                      int64_t n, int64_t* out);
+
+// phase launchers
+orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
+                       int n, int32_t* knn, double* rho2);
+orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
+                         const double* rho2, int64_t N, int d, int n,
+                         double t2, const uint8_t* eligible, int32_t* centers,
+                         int64_t* n_centers, int32_t* owner, int32_t* p);
+orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
+                           double t2, const orbf_weights_args* a);
+orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
+                       const int32_t* owner, const double* W,
+                       int64_t* row_ptr, int32_t* col, double* val);
+
+}  // namespace orbf

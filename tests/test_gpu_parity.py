@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: stencils, covering and CSR structure bit for bit; weights within a
+relative error of 1e-9 per row (max_j |w - w_ref| / max_j |w_ref|).
+Full-size node sets are checked on sampled rows that the oracle computes one
+by one, and by the covering invariants.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import nodesets
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def orbf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_03135_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(orbf):
+    return orbf.Context(0)
+
+
+def row_err(W, Wref):
+    den = np.abs(Wref).max(1)
+    return float((np.abs(W - Wref).max(1) / den).max())
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+CASES = {
+    "square45_d1": dict(kind="square", n=12, m=3, l=2, delta=1.0),
+    "square45_d05": dict(kind="square", n=12, m=3, l=2, delta=0.5),
+    "square45_d02": dict(kind="square", n=12, m=3, l=2, delta=0.2),
+    "disk5k_d05": dict(kind="disk", N=5000, n=31, m=5, l=4, delta=0.5),
+    "ball20k_d03": dict(kind="ball", N=20000, n=50, m=5, l=3, delta=0.3),
+    "ball1237_d0": dict(kind="ball", N=1237, n=20, m=3, l=2, delta=0.0),
+}
+
+
+def make(case):
+    c = CASES[case]
+    el = bnd = nrm = None
+    if c["kind"] == "square":
+        x = nodesets.square(45, 0)
+    elif c["kind"] == "disk":
+        D = nodesets.disk(c["N"], 200, 1)
+        x, el, bnd, nrm = D["x"], D["eligible"], D["boundary"], D["normals"]
+    else:
+        x = nodesets.ball(c["N"], 2)["x"]
+    return x, el, bnd, nrm, c
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_build_dm_matches_oracle(orbf, ctx, case):
+    x, el, bnd, nrm, c = make(case)
+    _say(f"[gpu] build_dm {case} N={len(x)} n={c['n']} delta={c['delta']}")
+    ref = oracle.build_dm(x, c["n"], c["m"], c["l"], c["delta"], eligible=el,
+                          boundary=bnd, normals=nrm)
+    got = orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"],
+                        eligible=None if el is None else gpu(el),
+                        boundary=None if bnd is None else gpu(bnd),
+                        normals=None if nrm is None else gpu(nrm), ctx=ctx)
+    knn = got["knn"].cpu().numpy()
+    assert np.array_equal(knn, ref["knn"])
+    assert np.array_equal(got["rho2"].cpu().numpy(), ref["rho2"])
+    owner = got["owner"].cpu().numpy()
+    assert np.array_equal(owner, ref["owner"])
+    nc = int(got["n_centers"].item())
+    assert np.array_equal(got["centers"].cpu().numpy()[:nc], ref["centers"])
+    p = got["p"].cpu().numpy()[:nc]
+    assert np.array_equal(p, np.bincount(owner[owner >= 0],
+                                         minlength=len(x))[ref["centers"]])
+    assert np.array_equal(got["row_ptr"].cpu().numpy(), ref["row_ptr"])
+    assert np.array_equal(got["col"].cpu().numpy(), ref["col"])
+    W = got["W"].cpu().numpy()
+    rows = owner >= 0
+    err = row_err(W[rows], ref["W"][rows])
+    _say(f"[gpu] {case}: N_delta={nc} max row rel err {err:.2e}")
+    assert err <= TOL
+    val = got["val"].cpu().numpy()
+    rp = ref["row_ptr"]
+    err_csr = row_err(val.reshape(-1, c["n"]), ref["val"].reshape(-1, c["n"]))
+    assert err_csr <= TOL
+    lam = got["lam"].cpu().numpy()
+    assert np.allclose(lam[rows], np.abs(ref["W"][rows]).sum(1), rtol=1e-8)
+
+
+def test_disk_full_size(orbf, ctx):
+    """2D disk, 99,400 interior + 600 boundary nodes, n = 31, l = 4, r^5,
+    delta = 0.5, Laplacian interior rows + normal-derivative boundary rows:
+    the whole DM against the oracle."""
+    D = nodesets.disk(99400, 600, 1)
+    x = D["x"]
+    _say(f"[gpu] disk full N={len(x)}")
+    ref = oracle.build_dm(x, 31, 5, 4, 0.5, eligible=D["eligible"],
+                          boundary=D["boundary"], normals=D["normals"])
+    got = orbf.build_dm(gpu(x), 31, 5, 4, 0.5, eligible=gpu(D["eligible"]),
+                        boundary=gpu(D["boundary"]), normals=gpu(D["normals"]),
+                        ctx=ctx)
+    assert np.array_equal(got["knn"].cpu().numpy(), ref["knn"])
+    assert np.array_equal(got["owner"].cpu().numpy(), ref["owner"])
+    assert np.array_equal(got["col"].cpu().numpy(), ref["col"])
+    err = row_err(got["W"].cpu().numpy(), ref["W"])
+    _say(f"[gpu] disk full: max row rel err {err:.2e}")
+    assert err <= TOL
+
+
+def test_ball_full_size_sampled(orbf, ctx):
+    """3D ball, N = 1,000,000, n = 50, l = 3, r^5, delta = 0.3: stencils of
+    sampled nodes by brute force, the covering in full (oracle grid kNN +
+    sequential greedy), weights of sampled rows one stencil at a time."""
+    x = nodesets.ball(1_000_000, 2)["x"]
+    n, m, l, delta = 50, 5, 3, 0.3
+    _say("[gpu] ball 1M build")
+    got = orbf.build_dm(gpu(x), n, m, l, delta, ctx=ctx)
+    knn = got["knn"].cpu().numpy()
+    rho2 = got["rho2"].cpu().numpy()
+    owner = got["owner"].cpu().numpy()
+    W = got["W"].cpu().numpy()
+    rng = np.random.default_rng(0)
+    sample = np.concatenate([[0, len(x) - 1], rng.choice(len(x), 60, False)])
+    for q in sample:
+        kq, rq = oracle.knn_one(x, n, q)
+        assert np.array_equal(knn[q], kq) and rho2[q] == rq, q
+    _say("[gpu] ball 1M: oracle covering")
+    ridx, rrho = oracle.knn(x, n, "grid")
+    assert np.array_equal(ridx, knn)
+    rown, rcen = oracle.cover(x, ridx, rrho, delta)
+    assert np.array_equal(rown, owner)
+    worst = 0.0
+    for e in rng.choice(len(x), 300, False):
+        k = rown[e]
+        st = ridx[k]
+        P = x[st]
+        w = oracle.stencil_weights(P, x[e][None, :], m, l)[0]
+        worst = max(worst, np.abs(W[e] - w).max() / np.abs(w).max())
+    _say(f"[gpu] ball 1M: sampled max row rel err {worst:.2e}")
+    assert worst <= TOL
+    rp = got["row_ptr"].cpu().numpy()
+    assert np.array_equal(rp, np.arange(len(x) + 1, dtype=np.int64) * n)
+
+
+def test_edge_cases(orbf, ctx):
+    # n == N (every stencil is the whole set), ragged tiny sizes
+    for N, d in ((7, 2), (33, 3), (65, 2)):
+        x = np.random.default_rng(N).random((N, d))
+        _say(f"[gpu] edge N=n={N} d={d}")
+        k, r = orbf.build_nodes_knn(ctx, gpu(x), N)
+        ctx.sync()
+        rk, rr = oracle.knn(x, N)
+        assert np.array_equal(k.cpu().numpy(), rk)
+        assert np.array_equal(r.cpu().numpy(), rr)
+    # n = 1: every stencil is the node itself
+    x = np.random.default_rng(3).random((100, 3))
+    k, r = orbf.build_nodes_knn(ctx, gpu(x), 1)
+    ctx.sync()
+    assert np.array_equal(k.cpu().numpy()[:, 0], np.arange(100))
+    assert (r.cpu().numpy() == 0).all()
+
+
+def test_errors(orbf, ctx):
+    x = np.random.default_rng(0).random((300, 2))
+    y = x.copy()
+    y[17] = y[5]
+    _say("[gpu] duplicate nodes")
+    orbf.build_nodes_knn(ctx, gpu(y), 8)
+    with pytest.raises(orbf.OrbfError) as e:
+        ctx.sync()
+    assert e.value.code == orbf.EDUPLICATE
+    ctx.sync()  # cleared
+    with pytest.raises(orbf.OrbfError) as e:
+        orbf.build_nodes_knn(ctx, gpu(x), 301)
+    assert e.value.code == orbf.EINVAL
+    k, r = orbf.build_nodes_knn(ctx, gpu(x), 8)
+    for bad in (-0.5, 1.5, math.nan):
+        with pytest.raises(orbf.OrbfError) as e:
+            orbf.select_overlapped_stencils(ctx, gpu(x), k, r, bad)
+        assert e.value.code == orbf.EINVAL
+    c, nc, o, p = orbf.select_overlapped_stencils(ctx, gpu(x), k, r, 0.5)
+    for m in (2, 1):
+        with pytest.raises(orbf.OrbfError):
+            orbf.compute_weights(ctx, orbf.OP_LAPLACIAN, m, 1, 8, 0.5, gpu(x),
+                                 k, r, centers=c, n_centers=nc, owner=o)
+    with pytest.raises(orbf.OrbfError):  # n < M
+        orbf.compute_weights(ctx, orbf.OP_LAPLACIAN, 3, 4, 8, 0.5, gpu(x), k,
+                             r, centers=c, n_centers=nc, owner=o)
+    ctx.sync()
+
+
+def test_bitwise_repeatable(orbf, ctx):
+    x = nodesets.ball(20000, 2)["x"]
+    a = orbf.build_dm(gpu(x), 50, 5, 3, 0.3, ctx=ctx)
+    b = orbf.build_dm(gpu(x), 50, 5, 3, 0.3, ctx=ctx)
+    for key in ("knn", "rho2", "owner", "W", "col", "val"):
+        assert torch.equal(a[key], b[key]), key
