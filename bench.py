@@ -136,7 +136,7 @@ def main():
                      "csr": ph[3]},
         "hbm_gbs": {"knn": knn_bytes / (ph[0] * 1e-3) / 1e9,
                     "csr": csr_bytes / (ph[3] * 1e-3) / 1e9},
-        "roofline": {"bound": "alu", "kernel": "weights_lds_kernel",
+        "roofline": {"bound": "alu", "kernel": "weights_reg_kernel<9,2>",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": None,

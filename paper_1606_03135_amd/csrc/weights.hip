@@ -14,6 +14,7 @@
 #include <math.h>
 
 #include "orbf_internal.hpp"
+#include "weights_common.hpp"
 
 namespace orbf {
 
@@ -25,24 +26,7 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-struct WeightsParams {
-  const double* xyz;
-  const int32_t* knn;
-  const double* rho2;
-  const int32_t* centers;   // mode b
-  const int64_t* n_centers; // mode b (device)
-  const int32_t* rows;      // mode a
-  int64_t n_rows;           // mode a
-  const int32_t* owner;     // mode b: row selection
-  int64_t N;
-  int32_t* owner_out;       // mode a
-  const double* normals;    // mode a, NEUMANN
-  const int8_t* ex;         // M*3 monomial exponents
-  double* W;
-  double* lebesgue;
-  DevStatus* st;
-  int d, n, m, M, K, op, pcap, ldm;
-};
+
 
 // r^k for odd k >= 1, from r2 = r^2
 __device__ __forceinline__ double odd_pow(double r2, int k) {
@@ -351,6 +335,7 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   P.d = d;
   P.n = n;
   P.m = m;
+  P.l = l;
   P.M = M;
   P.K = K;
   P.op = (int)op;
@@ -360,8 +345,10 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   const int64_t grid = work < (int64_t)ctx->num_cus * 64 ? work : (int64_t)ctx->num_cus * 64;
   if (grid <= 0) return ORBF_OK;
   hipEventRecord(ctx->ev[8], ctx->stream);
-  hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
-                     lds_bytes(pcap), ctx->stream, P);
+  static const bool force_lds = getenv("ORBF_WEIGHTS_LDS") != nullptr;
+  if (force_lds || !launch_weights_reg(ctx, P, grid))
+    hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
+                       lds_bytes(pcap), ctx->stream, P);
   hipEventRecord(ctx->ev[9], ctx->stream);
   ctx->phase_valid[4] = true;
   return hip_check(ctx, hipGetLastError(), "weights");

@@ -1,0 +1,139 @@
+// Shared pieces of the two weights kernels: launch parameters and the
+// operator formulas of the local saddle system (Sec. 4.1, eqs.
+// rbffd_linsys / orbffd_rhs) in scaled coordinates.
+#pragma once
+
+#include <math.h>
+
+#include "orbf_internal.hpp"
+
+namespace orbf {
+
+struct WeightsParams {
+  const double* xyz;
+  const int32_t* knn;
+  const double* rho2;
+  const int32_t* centers;   // covered rows: centers list (device)
+  const int64_t* n_centers; // covered rows: number of centers (device)
+  const int32_t* rows;      // explicit rows (each on its own stencil)
+  int64_t n_rows;
+  const int32_t* owner;     // covered rows: row e is computed by owner[e]
+  int64_t N;
+  int32_t* owner_out;       // explicit rows: owner[row] = row
+  const double* normals;    // explicit rows, NEUMANN: n_rows * d
+  const int8_t* ex;         // M * 3 monomial exponents, graded lex
+  double* W;                // N * n
+  double* lebesgue;         // N or null
+  DevStatus* st;
+  int d, n, m, l, M, K, op, pcap, ldm;
+};
+
+__device__ __forceinline__ double ipow_small(double v, int e) {
+  double r = 1.0;
+  for (int i = 0; i < e; ++i) r *= v;
+  return r;
+}
+
+// psi(p) = p0^e0 p1^e1 p2^e2
+__device__ __forceinline__ double monomial(const double* p, const int8_t* e,
+                                           int d) {
+  double v = ipow_small(p[0], e[0]) * ipow_small(p[1], e[1]);
+  if (d == 3) v *= ipow_small(p[2], e[2]);
+  return v;
+}
+
+// L psi at p: Laplacian sum_a e_a (e_a - 1) p^(e - 2 eps_a), or the normal
+// derivative sum_a nrm_a e_a p^(e - eps_a); the normal is passed as scalars
+__device__ __forceinline__ double monomial_op(const double* p,
+                                              const int8_t* e, int d, int op,
+                                              double n0, double n1,
+                                              double n2) {
+  const int e0 = e[0], e1 = e[1], e2 = (d == 3) ? e[2] : 0;
+  const double p0 = p[0], p1 = p[1], p2 = (d == 3) ? p[2] : 1.0;
+  double s = 0.0;
+  if (op == ORBF_OP_LAPLACIAN) {
+    if (e0 >= 2)
+      s += (double)(e0 * (e0 - 1)) *
+           (ipow_small(p0, e0 - 2) * ipow_small(p1, e1) * ipow_small(p2, e2));
+    if (e1 >= 2)
+      s += (double)(e1 * (e1 - 1)) *
+           (ipow_small(p0, e0) * ipow_small(p1, e1 - 2) * ipow_small(p2, e2));
+    if (e2 >= 2)
+      s += (double)(e2 * (e2 - 1)) *
+           (ipow_small(p0, e0) * ipow_small(p1, e1) * ipow_small(p2, e2 - 2));
+  } else {
+    if (e0 >= 1)
+      s += n0 * ((double)e0 * (ipow_small(p0, e0 - 1) * ipow_small(p1, e1) *
+                               ipow_small(p2, e2)));
+    if (e1 >= 1)
+      s += n1 * ((double)e1 * (ipow_small(p0, e0) * ipow_small(p1, e1 - 1) *
+                               ipow_small(p2, e2)));
+    if (e2 >= 1)
+      s += n2 * ((double)e2 * (ipow_small(p0, e0) * ipow_small(p1, e1) *
+                               ipow_small(p2, e2 - 1)));
+  }
+  return s;
+}
+
+// sqrt(x) for x >= 0 from the hardware reciprocal-square-root estimate and
+// two Newton steps on s^2 = x (accurate to a few ulp; 0 for x = 0)
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y;
+  const double h = 0.5 * y;
+  s = fma(fma(-s, s, x), h, s);
+  s = fma(fma(-s, s, x), h, s);
+  return x > 0.0 ? s : 0.0;
+}
+
+// |x|^m from r2 = |x|^2, m odd: r * r2^((m-1)/2)
+__device__ __forceinline__ double phs(double r2, int m) {
+  double p = sqrt_nr(r2);
+  for (int i = 0; i < (m - 1) / 2; ++i) p *= r2;
+  return p;
+}
+
+// L |x - x_j|^m at x, with (dx,dy,dz) = x - x_j and r2 = |x - x_j|^2:
+// Laplacian m (m + d - 2) r^(m-2); gradient m r^(m-2) (x - x_j) . nrm
+__device__ __forceinline__ double phs_op(double dx, double dy, double dz,
+                                         double r2, int m, int d, int op,
+                                         double n0, double n1, double n2) {
+  double p = sqrt_nr(r2);  // r^(m-2), m - 2 odd
+  for (int i = 0; i < (m - 3) / 2; ++i) p *= r2;
+  if (op == ORBF_OP_LAPLACIAN) return (double)(m * (m + d - 2)) * p;
+  const double dot = dx * n0 + dy * n1 + dz * n2;
+  return ((double)m * p) * dot;
+}
+
+// Monomials from a power table pw[a * (l + 1) + e] = p_a^e of one point.
+__device__ __forceinline__ double monomial_pw(const double* pw, int l1,
+                                              const int8_t* e) {
+  return pw[e[0]] * pw[l1 + e[1]] * pw[2 * l1 + e[2]];
+}
+
+// L psi from the power table: Laplacian sum_a e_a (e_a - 1) p^(e - 2 eps_a),
+// or the normal derivative sum_a n_a e_a p^(e - eps_a)
+__device__ __forceinline__ double monomial_op_pw(const double* pw, int l1,
+                                                 const int8_t* e, int op,
+                                                 double n0, double n1,
+                                                 double n2) {
+  const int e0 = e[0], e1 = e[1], e2 = e[2];
+  const double* p0 = pw;
+  const double* p1 = pw + l1;
+  const double* p2 = pw + 2 * l1;
+  double s = 0.0;
+  if (op == ORBF_OP_LAPLACIAN) {
+    if (e0 >= 2) s += (double)(e0 * (e0 - 1)) * (p0[e0 - 2] * p1[e1] * p2[e2]);
+    if (e1 >= 2) s += (double)(e1 * (e1 - 1)) * (p0[e0] * p1[e1 - 2] * p2[e2]);
+    if (e2 >= 2) s += (double)(e2 * (e2 - 1)) * (p0[e0] * p1[e1] * p2[e2 - 2]);
+  } else {
+    if (e0 >= 1) s += n0 * ((double)e0 * (p0[e0 - 1] * p1[e1] * p2[e2]));
+    if (e1 >= 1) s += n1 * ((double)e1 * (p0[e0] * p1[e1 - 1] * p2[e2]));
+    if (e2 >= 1) s += n2 * ((double)e2 * (p0[e0] * p1[e1] * p2[e2 - 1]));
+  }
+  return s;
+}
+
+bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid);
+
+}  // namespace orbf

@@ -1,0 +1,363 @@
+// Local RBF-FD weights with the saddle system held in registers
+// (Sec. 4.1, eqs. rbffd_linsys, orbffd_eq, orbffd_rhs).
+//
+// One wavefront per stencil center.  The K x (K + P) augmented matrix
+// [A_hat | B_hat] is distributed 2D block-cyclically over an 8 x 8 lane grid:
+// lane = r + 8 c holds rows i = 8 ii + r (ii < L) and columns j = 8 jj + c
+// (jj < L: A_hat; jj = L + jp: right-hand side e = 8 jp + c), K <= 8 L,
+// P <= 8 PL.  The trailing update is an L x (L + PL) register block per lane,
+// so all 64 lanes stay busy and every broadcast value is reused L times.
+//
+// Rows never move (implicit partial pivoting): a per-row mask retires a row
+// once it has served as a pivot, so every register index is a compile-time
+// constant.  Elimination step k = 8 kb + cc (kb unrolled, cc a uniform loop
+// counter) makes one LDS round trip:
+//   1. pivot search: the 8 lanes of column k reduce a 32-bit key
+//      (|a| high bits | local row) with DPP; readlane and a ballot give the
+//      pivot's row slot as wave-uniform values;
+//   2. the pivot row (read-only, one scalar-branch case) and the column of
+//      multipliers of the still-active rows go to LDS;
+//   3. every lane reads its pivot-row entries and multipliers and applies
+//      the rank-1 update to its L x (L + PL - kb) register block.
+// The elimination is Gauss-Jordan: the rows pivoted earlier are eliminated
+// too (they are in the register block anyway), so when the last step is done
+// the row slot pivoted at step j holds u_jj x_j in its right-hand-side
+// columns and no back substitution is needed.  Multipliers are not kept.
+// Padded slots (>= K) are inactive from the start and hold zeros.
+#include <math.h>
+
+#include <type_traits>
+
+#include "orbf_internal.hpp"
+#include "weights_common.hpp"
+
+namespace orbf {
+
+namespace {
+
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) {
+  return a > b ? a : b;
+}
+
+// max of a 32-bit key over each aligned group of 8 lanes (DPP, no LDS)
+__device__ __forceinline__ uint32_t group8_max(uint32_t k) {
+  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0xB1, 0xF, 0xF, false));
+  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0x4E, 0xF, 0xF, false));
+  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0x141, 0xF, 0xF, false));
+  return k;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// reciprocal of a wave-uniform value: hardware estimate + 2 Newton steps
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+
+template <int L, int PL>
+__global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
+  constexpr int LC = L + PL;
+  constexpr int S = 8 * L;  // row / column slots of A_hat
+  extern __shared__ double dyn_s[];  // psi (n x M) then L psi (8 PL x M)
+  __shared__ double xi_s[3 * S];
+  __shared__ int cols_s[S];
+  __shared__ int8_t ex_s[3 * 36];
+  __shared__ double ubuf[8 * LC];  // [c][jj] pivot row
+  __shared__ double lbuf[8 * L];   // [r][ii] multipliers
+  __shared__ double dinv[S];
+  __shared__ double strip[LC * 64];  // assembly staging, one row per lane
+  __shared__ int srank[S];         // elimination step of each row slot
+
+  const int lane = threadIdx.x;
+  const int r = lane & 7, c = lane >> 3;
+  const int n = P.n, K = P.K, d = P.d, M = P.M, m = P.m, op = P.op;
+  double* psi_s = dyn_s;           // psi_t(xi_q), q < n, t < M
+  double* lpsi_s = dyn_s + n * M;  // L psi_t at the evaluation points
+  double* pw_s = lpsi_s + 8 * PL * M;  // powers of the scaled coordinates
+  for (int t = lane; t < 3 * M; t += 64) ex_s[t] = P.ex[t];
+
+  const bool explicit_rows = P.rows != nullptr;
+  const int64_t total = explicit_rows ? P.n_rows : *P.n_centers;
+  for (int64_t ci = blockIdx.x; ci < total; ci += gridDim.x) {
+    const int32_t ck = explicit_rows ? P.rows[ci] : P.centers[ci];
+    if ((uint32_t)ck >= (uint64_t)P.N) {
+      if (lane == 0) report(P.st, ORBF_EINVAL, ck);
+      continue;
+    }
+    const int32_t* stn = P.knn + (int64_t)ck * n;
+    bool bad = false;
+    for (int q = lane; q < n; q += 64) bad |= (uint32_t)stn[q] >= (uint64_t)P.N;
+    if (__ballot(bad)) {
+      if (lane == 0) report(P.st, ORBF_EINVAL, ck);
+      continue;
+    }
+    double nrm[3] = {0.0, 0.0, 0.0};
+    if (explicit_rows && op == ORBF_OP_NEUMANN) {
+      nrm[0] = P.normals[ci * d];
+      nrm[1] = P.normals[ci * d + 1];
+      if (d == 3) nrm[2] = P.normals[ci * d + 2];
+    }
+    int ncol = 0;
+    if (explicit_rows) {
+      if (lane == 0) cols_s[0] = 0;
+      ncol = 1;
+    } else {
+      for (int q0 = 0; q0 < n; q0 += 64) {
+        const int q = q0 + lane;
+        const bool mine = q < n && P.owner[stn[q]] == ck;
+        const unsigned long long b = __ballot(mine);
+        if (mine) cols_s[ncol + __popcll(b & ((1ull << lane) - 1ull))] = q;
+        ncol += __popcll(b);
+      }
+    }
+    const double r2c = P.rho2[ck];
+    const double rho = sqrt(r2c);
+    const double inv_rho = 1.0 / rho;
+    const double* xc = P.xyz + (int64_t)ck * d;
+    for (int q = lane; q < n; q += 64) {
+      const double* xq = P.xyz + (int64_t)stn[q] * d;
+      xi_s[3 * q] = (xq[0] - xc[0]) * inv_rho;
+      xi_s[3 * q + 1] = (xq[1] - xc[1]) * inv_rho;
+      xi_s[3 * q + 2] = (d == 3) ? (xq[2] - xc[2]) * inv_rho : 0.0;
+    }
+    wsync();
+    // power table p_a^e, e <= l, of every stencil node (2D: p_2 = 0)
+    const int l1 = P.l + 1;
+    for (int t = lane; t < 3 * n; t += 64) {
+      const double v = xi_s[t];
+      double* pw = pw_s + t * l1;  // pw_s[(3q + a) l1 + e]
+      double acc = 1.0;
+      for (int e = 0; e < l1; ++e) {
+        pw[e] = acc;
+        acc *= v;
+      }
+    }
+    wsync();
+    for (int t = lane; t < n * M; t += 64) {
+      const int q = t / M, s = t - q * M;
+      psi_s[t] = monomial_pw(pw_s + 3 * q * l1, l1, ex_s + 3 * s);
+    }
+    const double sinv = 1.0 / ((op == ORBF_OP_LAPLACIAN) ? r2c : rho);
+
+    for (int cb = 0; cb < ncol; cb += 8 * PL) {
+      const int nb = min(8 * PL, ncol - cb);
+      wsync();
+      for (int t = lane; t < nb * M; t += 64) {
+        const int e = t / M, s = t - e * M;
+        lpsi_s[t] = monomial_op_pw(pw_s + 3 * cols_s[cb + e] * l1, l1,
+                                   ex_s + 3 * s, op, nrm[0], nrm[1], nrm[2]);
+      }
+      wsync();
+      // ---- assemble [A_hat | B_hat] ----
+      // Entries of local row ii are computed by a compact runtime loop into
+      // this lane's LDS strip and read back into registers: no per-entry
+      // code duplication, and each lane reads only its own writes.
+      double a[L][LC];
+      sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+        constexpr int ii = decltype(iic)::value;
+        const int i = 8 * ii + r;
+        const bool ri = i < n;
+        const double xi0 = ri ? xi_s[3 * i] : 0.0;
+        const double xi1 = ri ? xi_s[3 * i + 1] : 0.0;
+        const double xi2 = ri ? xi_s[3 * i + 2] : 0.0;
+#pragma clang loop unroll(disable)
+        for (int jj = 0; jj < LC; ++jj) {
+          double v = 0.0;
+          if (jj < L) {
+            const int j = 8 * jj + c;
+            if (i < n && j < n) {
+              const double dx = xi0 - xi_s[3 * j], dy = xi1 - xi_s[3 * j + 1];
+              const double dz = xi2 - xi_s[3 * j + 2];
+              v = phs(dx * dx + dy * dy + dz * dz, m);
+            } else if (i < n && j < K) {
+              v = psi_s[i * M + (j - n)];
+            } else if (j < n && i < K) {
+              v = psi_s[j * M + (i - n)];
+            }
+          } else {
+            const int e = 8 * (jj - L) + c;
+            if (e < nb && i < K) {
+              const double* pe = xi_s + 3 * cols_s[cb + e];
+              if (i < n) {
+                const double dx = pe[0] - xi0, dy = pe[1] - xi1;
+                const double dz = pe[2] - xi2;
+                v = phs_op(dx, dy, dz, dx * dx + dy * dy + dz * dz, m, d, op,
+                           nrm[0], nrm[1], nrm[2]);
+              } else {
+                v = lpsi_s[e * M + (i - n)];
+              }
+            }
+          }
+          strip[jj * 64 + lane] = v;
+        }
+        sfor<0, LC>([&](auto jjc) __attribute__((always_inline)) {
+          constexpr int jj = decltype(jjc)::value;
+          a[ii][jj] = strip[jj * 64 + lane];
+        });
+      });
+      // ---- LU with row partial pivoting, rows kept in place ----
+      // act[ii]: magnitude mask of local row ii (0 once the row has been
+      // used as a pivot).  Pivoted rows keep their U entries and receive
+      // zero multipliers from then on.
+      uint32_t act[L];
+      sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+        constexpr int ii = decltype(iic)::value;
+        act[ii] = (8 * ii + r < K) ? 0x7FFFFF80u : 0u;
+      });
+      bool singular = false;
+      sfor<0, L>([&](auto kbc) __attribute__((always_inline)) {
+        constexpr int kb = decltype(kbc)::value;
+#pragma clang loop unroll(disable)
+        for (int cc = 0; cc < 8; ++cc) {
+          const int k = 8 * kb + cc;
+          if (k >= K) break;
+          // 1. pivot search down column k among the rows still active
+          uint32_t key0 = 0;
+          sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+            constexpr int ii = decltype(iic)::value;
+            const uint32_t hi = (uint32_t)__double2hiint(a[ii][kb]);
+            key0 = umax(key0, (hi & act[ii]) | (uint32_t)ii);
+          });
+          const uint32_t kmax = __builtin_amdgcn_readlane(group8_max(key0), 8 * cc);
+          if ((kmax & 0x7FFFFF80u) == 0u) singular = true;
+          const int iip = (int)(kmax & 15u);
+          const unsigned long long who =
+              __ballot(key0 == kmax) & (0xFFull << (8 * cc));
+          const int rp = (__ffsll((long long)who) - 1) & 7;
+          const int piv = 8 * iip + rp;
+          // 2. retire the pivot row; write it, and the column of unscaled
+          //    multipliers, to LDS
+          sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+            constexpr int ii = decltype(iic)::value;
+            act[ii] = (ii == iip && r == rp) ? 0u : act[ii];
+          });
+          sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+            constexpr int ii = decltype(iic)::value;
+            if (iip == ii) {
+              __asm__ volatile("; pivot row out %0" ::"i"(ii));
+              if (r == rp) {
+                sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
+                  constexpr int jj = decltype(jjc)::value;
+                  ubuf[c * LC + jj] = a[ii][jj];
+                });
+              }
+            }
+          });
+          if (c == cc) {
+            sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+              constexpr int ii = decltype(iic)::value;
+              lbuf[r * L + ii] = a[ii][kb];
+            });
+          }
+          if (lane == 0) srank[piv] = k;
+          wsync();
+          const double upiv = ubuf[cc * LC + kb];
+          if (!(upiv != 0.0)) singular = true;
+          const double dk = singular ? 0.0 : recip(upiv);
+          if (lane == 0) dinv[k] = dk;
+          // 3. rank-1 update
+          double u[LC];
+          sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
+            constexpr int jj = decltype(jjc)::value;
+            u[jj] = ubuf[c * LC + jj];
+          });
+          // Gauss-Jordan: every row but the pivot row is eliminated, the
+          // rows pivoted earlier included, so no back substitution follows
+          sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+            constexpr int ii = decltype(iic)::value;
+            const bool is_piv = ii == iip && r == rp;
+            const double l = is_piv ? 0.0 : lbuf[r * L + ii] * dk;
+            sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
+              constexpr int jj = decltype(jjc)::value;
+              a[ii][jj] = fma(-l, u[jj], a[ii][jj]);
+            });
+          });
+          wsync();
+        }
+      });
+      // ---- solution: the row slot pivoted at step j holds u_jj x_j ----
+      int rank[L];
+      double rdk[L];
+      sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+        constexpr int ii = decltype(iic)::value;
+        const bool live = 8 * ii + r < K;
+        rank[ii] = live ? srank[8 * ii + r] : 1 << 20;
+        rdk[ii] = live ? dinv[rank[ii]] : 0.0;
+      });
+      // ---- unscale, write rows, Lebesgue values ----
+      // row slot with rank j holds the unknown x_j; weights are x_j, j < n
+      if (singular && lane == 0) report(P.st, ORBF_ESINGULAR, ck);
+      sfor<0, PL>([&](auto jpc) __attribute__((always_inline)) {
+        constexpr int jp = decltype(jpc)::value;
+        const int e = 8 * jp + c;
+        const bool live = e < nb;
+        const int32_t row = live ? stn[cols_s[cb + e]] : 0;
+        double lam = 0.0;
+        sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+          constexpr int ii = decltype(iic)::value;
+          const int j = rank[ii];
+          if (live && j < n) {
+            const double w = singular ? NAN : (a[ii][L + jp] * rdk[ii]) * sinv;
+            P.W[(int64_t)row * n + j] = w;
+            lam += fabs(w);
+          }
+        });
+        lam += __shfl_xor(lam, 1, 64);
+        lam += __shfl_xor(lam, 2, 64);
+        lam += __shfl_xor(lam, 4, 64);
+        if (live && r == 0) {
+          if (P.lebesgue) P.lebesgue[row] = lam;
+          if (explicit_rows && P.owner_out) P.owner_out[row] = row;
+        }
+      });
+      wsync();
+    }
+  }
+}
+
+}  // namespace
+
+// Launch the register kernel if a variant covers K; returns false otherwise.
+bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid) {
+  if (P.M > 35) return false;
+  const size_t dyn = ((size_t)(P.n + 8 * 2) * P.M + (size_t)3 * P.n * (P.l + 1)) *
+                     sizeof(double);
+#define ORBF_REG_CASE(LL, PP)                                               \
+  if (P.K <= 8 * LL) {                                                      \
+    hipLaunchKernelGGL((weights_reg_kernel<LL, PP>), dim3((unsigned)grid),   \
+                       dim3(64), dyn, ctx->stream, P);                      \
+    return true;                                                            \
+  }
+  ORBF_REG_CASE(3, 2)
+  ORBF_REG_CASE(4, 2)
+  ORBF_REG_CASE(5, 2)
+  ORBF_REG_CASE(6, 2)
+  ORBF_REG_CASE(7, 2)
+  ORBF_REG_CASE(8, 2)
+  ORBF_REG_CASE(9, 2)
+#undef ORBF_REG_CASE
+  return false;
+}
+
+}  // namespace orbf
