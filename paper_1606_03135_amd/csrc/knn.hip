@@ -7,11 +7,11 @@
 //   3. scatter into a cell-sorted copy of the coordinates,
 //   4. one wavefront per query scans the (2R+1)^d block of cells around its
 //      own cell, R = 1, 2, ... until the n-th key is provably inside the
-//      scanned block; the candidates are staged in LDS through a 64-bin
-//      histogram on d^2 that isolates the n nearest plus a few extra, which
-//      are then ranked exactly by (d^2, index).
-// Queries run in cell order so that neighbouring wavefronts reuse the same
-// candidate cells from L2.
+//      scanned block; candidates below a threshold are compacted into LDS in
+//      one pass and ranked exactly by (d^2, index).
+// Each wavefront takes a run of consecutive queries in cell order: they
+// share candidate cells (L2 reuse) and nearly the same stencil radius, which
+// seeds the threshold of the next query.
 #include <math.h>
 
 #include "orbf_internal.hpp"
@@ -21,9 +21,8 @@ namespace orbf {
 namespace {
 
 constexpr int kWaves = 4;    // wavefronts per block in the query kernel
-constexpr int kBins = 64;    // histogram bins (one per lane)
 constexpr int kKeep = 256;   // LDS capacity for ranked candidates per wave
-constexpr int kLevels = 6;   // histogram refinements before giving up
+constexpr int kRun = 16;     // consecutive (cell-ordered) queries per wave
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -192,202 +191,129 @@ __global__ __launch_bounds__(256) void cell_scatter_kernel(
   }
 }
 
-// Histogram classification of a squared distance across refinement levels:
-// returns -1 (below the selected bin: keep), 0 (in the selected bin of the
-// deepest level), +1 (discard).  `lev` levels are fully decided; the
-// deepest level's bin is returned through *bin.
-struct Levels {
-  double lo[kLevels];
-  double scale[kLevels];
-  int star[kLevels];
-  int n;  // number of decided levels
-};
-
-__device__ __forceinline__ int bin_of(double d2, double lo, double scale) {
-  double t = (d2 - lo) * scale;
-  int b = (t > 0.0) ? (int)t : 0;
-  return b >= kBins ? kBins - 1 : b;
-}
-
-// Classify d2 (already known < cut) against the decided levels.  Returns
-// -1 keep, +1 drop, 0 undecided (then *bin holds the bin at the next level).
-__device__ __forceinline__ int classify(double d2, const Levels& L, double lo,
-                                        double scale, int* bin) {
-#pragma unroll
-  for (int k = 0; k < kLevels; ++k) {
-    if (k < L.n) {
-      int b = bin_of(d2, L.lo[k], L.scale[k]);
-      if (b < L.star[k]) return -1;
-      if (b > L.star[k]) return 1;
-    }
-  }
-  *bin = bin_of(d2, lo, scale);
-  return 0;
-}
-
+// One wavefront per query.  Candidates with d^2 < T are compacted into LDS
+// in one pass and ranked exactly by (d^2, index); T starts from the previous
+// query's n-th distance (queries run in cell order, so neighbours have
+// nearly the same stencil radius) and is corrected by bisection when the
+// pass keeps fewer than n or more than kKeep candidates.  T never exceeds
+// the squared distance to the boundary of the scanned block, so the result
+// is exact: every node outside the block is farther than every kept one.
 __global__ __launch_bounds__(256) void knn_query_kernel(
     const double* __restrict__ xs, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ cstart, const GridParams* __restrict__ gpp,
     int64_t N, int d, int n, int32_t* __restrict__ knn,
     double* __restrict__ rho2, DevStatus* __restrict__ st) {
-  __shared__ int hist[kWaves][kBins];
   __shared__ double kd[kWaves][kKeep];
   __shared__ int kj[kWaves][kKeep];
-  __shared__ int kcnt[kWaves];
+  __shared__ double kth[kWaves];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const GridParams g = *gpp;
+  double est = 0.0;  // previous query's n-th squared distance (0: none)
+  const int64_t q_begin = ((int64_t)blockIdx.x * kWaves + w) * kRun;
+  const int64_t q_end = min(q_begin + kRun, N);
 
-  for (int64_t qs = (int64_t)blockIdx.x * kWaves + w; qs < N;
-       qs += (int64_t)gridDim.x * kWaves) {
+  for (int64_t qs = q_begin; qs < q_end; ++qs) {
     const int32_t qi = perm[qs];
     const double q0 = xs[qs * d], q1 = xs[qs * d + 1];
     const double q2 = (d == 3) ? xs[qs * d + 2] : 0.0;
-    const double qv[3] = {q0, q1, q2};
-    int cq[3];
-    cq[0] = cell_coord(q0, g, 0);
-    cq[1] = cell_coord(q1, g, 1);
-    cq[2] = (d == 3) ? cell_coord(q2, g, 2) : 0;
+    const int cq0 = cell_coord(q0, g, 0), cq1 = cell_coord(q1, g, 1);
+    const int cq2 = (d == 3) ? cell_coord(q2, g, 2) : 0;
     bool dup = false;
+    bool done = false;
 
-    for (int R = 1;; ++R) {
-      int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int R = 1; !done; ++R) {
+      const int lo0 = max(cq0 - R, 0), hi0 = min(cq0 + R, g.nc[0] - 1);
+      const int lo1 = max(cq1 - R, 0), hi1 = min(cq1 + R, g.nc[1] - 1);
+      const int lo2 = (d == 3) ? max(cq2 - R, 0) : 0;
+      const int hi2 = (d == 3) ? min(cq2 + R, g.nc[2] - 1) : 0;
       bool whole = true;
       double b = INFINITY;
-      for (int a = 0; a < d; ++a) {
-        lo[a] = max(cq[a] - R, 0);
-        hi[a] = min(cq[a] + R, g.nc[a] - 1);
-        if (cq[a] - R > 0) {
-          b = fmin(b, qv[a] - (g.lo[a] + (double)(cq[a] - R) * g.s));
-          whole = false;
-        }
-        if (cq[a] + R < g.nc[a] - 1) {
-          b = fmin(b, (g.lo[a] + (double)(cq[a] + R + 1) * g.s) - qv[a]);
-          whole = false;
-        }
+      if (cq0 - R > 0) { b = fmin(b, q0 - (g.lo[0] + (double)(cq0 - R) * g.s)); whole = false; }
+      if (cq0 + R < g.nc[0] - 1) { b = fmin(b, (g.lo[0] + (double)(cq0 + R + 1) * g.s) - q0); whole = false; }
+      if (cq1 - R > 0) { b = fmin(b, q1 - (g.lo[1] + (double)(cq1 - R) * g.s)); whole = false; }
+      if (cq1 + R < g.nc[1] - 1) { b = fmin(b, (g.lo[1] + (double)(cq1 + R + 1) * g.s) - q1); whole = false; }
+      if (d == 3) {
+        if (cq2 - R > 0) { b = fmin(b, q2 - (g.lo[2] + (double)(cq2 - R) * g.s)); whole = false; }
+        if (cq2 + R < g.nc[2] - 1) { b = fmin(b, (g.lo[2] + (double)(cq2 + R + 1) * g.s) - q2); whole = false; }
       }
       // unscanned nodes are at least b away; the margin absorbs rounding in
       // d^2, in b and in the cell assignment
       const double cut = whole ? g.diag2 : b * b * (1.0 - 1e-9);
 
-      // walk the candidate rows (runs of cells contiguous along x)
-      auto for_candidates = [&](auto&& f) {
-        for (int z = lo[2]; z <= hi[2]; ++z)
-          for (int y = lo[1]; y <= hi[1]; ++y) {
+      double tlo = 0.0, thi = cut;  // bisection bracket for T
+      double T = (est > 0.0 && est * 1.3 < cut) ? est * 1.3 : cut;
+      for (int it = 0; it < 64; ++it) {
+        // one pass: compact every candidate with d^2 < T
+        int base = 0;
+        for (int z = lo2; z <= hi2; ++z)
+          for (int y = lo1; y <= hi1; ++y) {
             const int64_t crow = ((int64_t)z * g.nc[1] + y) * g.nc[0];
-            const int64_t s0 = cstart[crow + lo[0]];
-            const int64_t s1 = cstart[crow + hi[0] + 1];
-            for (int64_t t = s0 + lane; t < s1; t += 64) f(t);
+            const int64_t s0 = cstart[crow + lo0];
+            const int64_t s1 = cstart[crow + hi0 + 1];
+            for (int64_t t0 = s0; t0 < s1; t0 += 64) {
+              const int64_t t = t0 + lane;
+              bool keep = false;
+              double d2 = 0.0;
+              if (t < s1) {
+                const double* p = xs + t * d;
+                d2 = exact_sqdist(q0, q1, q2, p[0], p[1], d == 3 ? p[2] : 0.0, d);
+                if (d2 == 0.0 && t != qs) dup = true;
+                keep = d2 < T;
+              }
+              const unsigned long long m = __ballot(keep);
+              if (keep) {
+                const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (pos < kKeep) {
+                  kd[w][pos] = d2;
+                  kj[w][pos] = perm[t];
+                }
+              }
+              base += __popcll(m);
+            }
           }
-      };
-      auto dist = [&](int64_t t) {
-        const double* p = xs + t * d;
-        return exact_sqdist(q0, q1, q2, p[0], p[1], d == 3 ? p[2] : 0.0, d);
-      };
-
-      Levels L;
-      L.n = 0;
-      double hlo = 0.0, hscale = (double)kBins / cut;
-      int base = 0;  // candidates below every selected bin so far
-      int star = 0, kept = 0;
-      bool ok = false;
-      for (int lev = 0; lev <= kLevels; ++lev) {
-        hist[w][lane] = 0;
-        wave_sync();
-        int cnt = 0;
-        for_candidates([&](int64_t t) {
-          double d2 = dist(t);
-          if (lev == 0 && d2 == 0.0 && t != qs) dup = true;
-          if (!(d2 < cut)) return;
-          int bn;
-          if (classify(d2, L, hlo, hscale, &bn) == 0) {
-            atomicAdd(&hist[w][bn], 1);
-            ++cnt;
-          }
-        });
-        wave_sync();
-        if (lev == 0) {
-          if (wave_sum(cnt) < n) break;  // block too small: grow R
-        }
-        // inclusive prefix over the bins (bin = lane)
-        int c = hist[w][lane];
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          int u = __shfl_up(c, o, 64);
-          if (lane >= o) c += u;
-        }
-        const int need = n - base;
-        const unsigned long long m = __ballot(c >= need);
-        star = __ffsll((long long)m) - 1;
-        const int cum_star = __shfl(c, star, 64);
-        const int below = (star > 0) ? __shfl(c, star - 1, 64) : 0;
-        kept = base + cum_star;
-        if (kept <= kKeep) {
-          ok = true;
-          break;
-        }
-        if (lev == kLevels) break;
-        // refine inside the selected bin
-        L.lo[lev] = hlo;
-        L.scale[lev] = hscale;
-        L.star[lev] = star;
-        L.n = lev + 1;
-        base += below;
-        const double wbin = 1.0 / hscale;
-        hlo = hlo + (double)star * wbin;
-        hscale = (double)kBins / wbin;
-      }
-      if (!ok) {
-        bool small = false;
-        if (L.n == 0) {
-          // fewer than n candidates inside the provable radius
-          small = true;
-        }
-        if (small) {
-          if (whole) {  // cannot happen with N >= n; guard the loop
-            if (lane == 0) report(st, ORBF_EINTERNAL, qi);
-            break;
-          }
+        if (base < n) {
+          if (T >= cut) break;  // too few inside the provable radius: grow R
+          tlo = T;
+          T = (thi < cut) ? 0.5 * (T + thi) : fmin(cut, T * 1.6);
           continue;
         }
+        if (base > kKeep) {
+          thi = T;
+          T = 0.5 * (tlo + T);
+          continue;
+        }
+        // exact rank by (d^2, index); ranks below n are the stencil
+        wave_sync();
+        for (int t = lane; t < base; t += 64) {
+          const double dt = kd[w][t];
+          const int jt = kj[w][t];
+          int r = 0;
+          for (int u = 0; u < base; ++u) {
+            const double du = kd[w][u];
+            const int ju = kj[w][u];
+            r += (du < dt) || (du == dt && ju < jt);
+          }
+          if (r < n) {
+            knn[(int64_t)qi * n + r] = jt;
+            if (r == n - 1) {
+              rho2[qi] = dt;
+              kth[w] = dt;  // n-th distance, the next query's first guess
+            }
+          }
+        }
+        wave_sync();
+        est = kth[w];
+        done = true;
+        break;
+      }
+      if (!done && whole) {  // cannot happen with N >= n finite nodes
         if (lane == 0) report(st, ORBF_EINTERNAL, qi);
         break;
       }
-
-      // stage the kept candidates in LDS
-      if (lane == 0) kcnt[w] = 0;
-      wave_sync();
-      for_candidates([&](int64_t t) {
-        double d2 = dist(t);
-        if (!(d2 < cut)) return;
-        int bn;
-        int cl = classify(d2, L, hlo, hscale, &bn);
-        if (cl < 0 || (cl == 0 && bn <= star)) {
-          int slot = atomicAdd(&kcnt[w], 1);
-          if (slot < kKeep) {
-            kd[w][slot] = d2;
-            kj[w][slot] = perm[t];
-          }
-        }
-      });
-      wave_sync();
-      const int K = min(kcnt[w], kKeep);
-      // exact rank by (d2, index); ranks below n are the stencil
-      for (int t = lane; t < K; t += 64) {
-        const double dt = kd[w][t];
-        const int jt = kj[w][t];
-        int r = 0;
-        for (int u = 0; u < K; ++u) {
-          const double du = kd[w][u];
-          const int ju = kj[w][u];
-          r += (du < dt) || (du == dt && ju < jt);
-        }
-        if (r < n) {
-          knn[(int64_t)qi * n + r] = jt;
-          if (r == n - 1) rho2[qi] = dt;
-        }
+      if (!done && T < cut) {  // bisection did not converge (ties)
+        if (lane == 0) report(st, ORBF_EINTERNAL, qi);
+        break;
       }
-      wave_sync();
-      break;
     }
     if (__ballot(dup) && lane == 0) report(st, ORBF_EDUPLICATE, qi);
   }
@@ -425,9 +351,8 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   if (st) return st;
   hipLaunchKernelGGL(cell_scatter_kernel, dim3(g1), dim3(256), 0, s, xyz, N, d,
                      cell_of, rank, cstart, perm, xs);
-  const int64_t qblocks = (N + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(knn_query_kernel,
-                     dim3((unsigned)(qblocks < (1 << 20) ? qblocks : (1 << 20))),
+  const int64_t qblocks = (N + kWaves * kRun - 1) / (kWaves * kRun);
+  hipLaunchKernelGGL(knn_query_kernel, dim3((unsigned)qblocks),
                      dim3(64 * kWaves), 0, s, xs, perm, cstart, gp, N, d, n,
                      knn, rho2, ctx->status);
   return hip_check(ctx, hipGetLastError(), "knn");
