@@ -256,8 +256,16 @@ def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
     if own_ctx:
         ctx = Context(xyz.device.index or 0)
     knn, rho2 = build_nodes_knn(ctx, xyz, n)
-    centers, n_centers, owner, p = select_overlapped_stencils(
-        ctx, xyz, knn, rho2, delta, eligible)
+    if math.isinf(tau):
+        centers, n_centers, owner, p = select_overlapped_stencils(
+            ctx, xyz, knn, rho2, delta, eligible)
+    else:
+        # the covering with the Lebesgue test is made by compute_weights
+        N = xyz.shape[0]
+        centers = torch.empty(N, dtype=torch.int32, device=xyz.device)
+        n_centers = torch.zeros(1, dtype=torch.int64, device=xyz.device)
+        owner = torch.empty(N, dtype=torch.int32, device=xyz.device)
+        p = None
     lam = torch.zeros(xyz.shape[0], dtype=torch.float64, device=xyz.device)
     W = compute_weights(ctx, OP_LAPLACIAN, m, l, n, delta, xyz, knn, rho2,
                         centers=centers, n_centers=n_centers, owner=owner,

@@ -242,8 +242,6 @@ orbf_status orbf_compute_weights(orbf_ctx* ctx, orbf_op op, int m, int l,
                   "covered rows use the Laplacian; list boundary rows explicitly");
     if (!a->centers || !a->n_centers || !a->owner)
       return fail(ctx, ORBF_EINVAL, "NULL covering pointer");
-    if (!isinf(a->tau))
-      return fail(ctx, ORBF_EINVAL, "finite tau is not supported yet");
   }
   hipSetDevice(ctx->device);
   const double t = 1.0 - delta;

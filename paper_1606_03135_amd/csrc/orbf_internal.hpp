@@ -65,7 +65,7 @@ struct orbf_ctx {
   std::string err;
   orbf::DevStatus* status = nullptr;  // device
   orbf::DevStatus* status_host = nullptr;  // pinned mirror
-  orbf::Buffer buf[24];
+  orbf::Buffer buf[32];
   int num_cus = 256;
   hipEvent_t ev[10] = {};
   float phase_ms[5] = {0, 0, 0, 0, 0};
@@ -96,6 +96,7 @@ enum BufId {
   B_ROWPTR_TMP,
   B_W_TMP,
   B_MISC,
+  B_MISC2,
 };
 
 // ctx helpers (api.hip)

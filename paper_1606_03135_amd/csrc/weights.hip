@@ -331,6 +331,9 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   P.ex = dex;
   P.W = a->W;
   P.lebesgue = a->lebesgue;
+  P.ball = nullptr;
+  P.accept = nullptr;
+  P.tau = a->tau;
   P.st = ctx->status;
   P.d = d;
   P.n = n;
@@ -341,6 +344,12 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   P.op = (int)op;
   P.pcap = pcap;
   P.ldm = K + pcap;
+  if (!explicit_rows && !isinf(a->tau)) {
+    // covering with the L-Lebesgue test first; rows below use its owners
+    st = launch_lebesgue_cover(ctx, P, t2, a->eligible, a->centers,
+                               a->n_centers, a->owner);
+    if (st) return st;
+  }
   const int64_t work = explicit_rows ? a->n_rows : a->N;
   const int64_t grid = work < (int64_t)ctx->num_cus * 64 ? work : (int64_t)ctx->num_cus * 64;
   if (grid <= 0) return ORBF_OK;

@@ -24,6 +24,11 @@ struct WeightsParams {
   const int8_t* ex;         // M * 3 monomial exponents, graded lex
   double* W;                // N * n
   double* lebesgue;         // N or null
+  // acceptance mode (Lebesgue covering): solve the ball columns of each
+  // listed center plus its reference column and record which pass
+  const uint64_t* ball;     // 2 words per node: ball positions q (j > c)
+  uint64_t* accept;         // 2 words per node: accepted positions q
+  double tau;
   DevStatus* st;
   int d, n, m, l, M, K, op, pcap, ldm;
 };
@@ -135,5 +140,9 @@ __device__ __forceinline__ double monomial_op_pw(const double* pw, int l1,
 }
 
 bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid);
+orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
+                                  double t2, const uint8_t* eligible,
+                                  int32_t* centers, int64_t* n_centers,
+                                  int32_t* owner);
 
 }  // namespace orbf

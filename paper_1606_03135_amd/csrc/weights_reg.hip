@@ -88,6 +88,10 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
   __shared__ double dinv[S];
   __shared__ double strip[LC * 64];  // assembly staging, one row per lane
   __shared__ int srank[S];         // elimination step of each row slot
+  __shared__ double lam_s[S + 1];  // acceptance mode: Lambda per column
+  __shared__ double dif_s[3 * S];  // acceptance mode: x_q - x_k
+  __shared__ int refcol_s;
+  __shared__ unsigned long long accw_s[2];
 
   const int lane = threadIdx.x;
   const int r = lane & 7, c = lane >> 3;
@@ -118,8 +122,71 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
       nrm[1] = P.normals[ci * d + 1];
       if (d == 3) nrm[2] = P.normals[ci * d + 2];
     }
-    int ncol = 0;
-    if (explicit_rows) {
+    int ncol = 0, nball = 0;
+    const bool accept_mode = P.accept != nullptr;
+    if (accept_mode) {
+      // columns: the center, its ball, and the stencil node nearest the
+      // stencil centroid (Sec. 4.2.1), found exactly as the sequential
+      // rule does: offsets x_q - x_k summed in stencil order, squared
+      // distances ((e0*e0)+(e1*e1))+(e2*e2), first minimum
+      const double* xc = P.xyz + (int64_t)ck * d;
+      for (int q = lane; q < n; q += 64) {
+        const double* xq = P.xyz + (int64_t)stn[q] * d;
+        dif_s[3 * q] = xq[0] - xc[0];
+        dif_s[3 * q + 1] = xq[1] - xc[1];
+        dif_s[3 * q + 2] = (d == 3) ? xq[2] - xc[2] : 0.0;
+      }
+      wsync();
+      double cen[3] = {0.0, 0.0, 0.0};
+      if (lane == 0) {
+#pragma clang fp contract(off)
+        for (int q = 0; q < n; ++q)
+          for (int a = 0; a < 3; ++a) cen[a] = cen[a] + dif_s[3 * q + a];
+        for (int a = 0; a < 3; ++a) cen[a] = cen[a] / (double)n;
+      }
+      for (int a = 0; a < 3; ++a) cen[a] = __shfl(cen[a], 0, 64);
+      double bd = INFINITY;
+      int bq = n;
+      for (int q = lane; q < n; q += 64) {
+        const double s = exact_sqdist(dif_s[3 * q], dif_s[3 * q + 1],
+                                      dif_s[3 * q + 2], cen[0], cen[1],
+                                      cen[2], d);
+        if (s < bd) {
+          bd = s;
+          bq = q;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(bd, o, 64);
+        const int oq = __shfl_xor(bq, o, 64);
+        if (ob < bd || (ob == bd && oq < bq)) {
+          bd = ob;
+          bq = oq;
+        }
+      }
+      const uint64_t b0 = P.ball[2 * (int64_t)ck], b1 = P.ball[2 * (int64_t)ck + 1];
+      for (int q0 = 0; q0 < n; q0 += 64) {
+        const int q = q0 + lane;
+        const uint64_t word = (q < 64) ? b0 : b1;
+        const bool mine = q < n && (q == 0 || ((word >> (q & 63)) & 1ull));
+        const unsigned long long b = __ballot(mine);
+        if (mine) cols_s[ncol + __popcll(b & ((1ull << lane) - 1ull))] = q;
+        if (mine && q == bq) refcol_s = ncol + __popcll(b & ((1ull << lane) - 1ull));
+        ncol += __popcll(b);
+      }
+      const uint64_t rw = (bq < 64) ? b0 : b1;
+      const bool ref_in = bq == 0 || ((rw >> (bq & 63)) & 1ull);
+      nball = ncol;
+      if (!ref_in) {
+        if (lane == 0) {
+          cols_s[ncol] = bq;
+          refcol_s = ncol;
+        }
+        ++ncol;
+      }
+      if (lane == 0) accw_s[0] = accw_s[1] = 0ull;
+    } else if (explicit_rows) {
       if (lane == 0) cols_s[0] = 0;
       ncol = 1;
     } else {
@@ -319,7 +386,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
           const int j = rank[ii];
           if (live && j < n) {
             const double w = singular ? NAN : (a[ii][L + jp] * rdk[ii]) * sinv;
-            P.W[(int64_t)row * n + j] = w;
+            if (!accept_mode) P.W[(int64_t)row * n + j] = w;
             lam += fabs(w);
           }
         });
@@ -327,10 +394,31 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         lam += __shfl_xor(lam, 2, 64);
         lam += __shfl_xor(lam, 4, 64);
         if (live && r == 0) {
-          if (P.lebesgue) P.lebesgue[row] = lam;
-          if (explicit_rows && P.owner_out) P.owner_out[row] = row;
+          if (accept_mode) {
+            lam_s[cb + e] = lam;
+          } else {
+            if (P.lebesgue) P.lebesgue[row] = lam;
+            if (explicit_rows && P.owner_out) P.owner_out[row] = row;
+          }
         }
       });
+      wsync();
+    }
+    if (accept_mode) {
+      // keep node e iff it is the center or Lambda_e <= tau * Lambda_ref
+      // (eq. calLstab with the threshold tau)
+      const double lref = lam_s[refcol_s];
+      for (int e = lane; e < nball; e += 64) {  // the appended reference
+                                                // column is not a row
+        const int q = cols_s[e];
+        const bool acc = q == 0 || lam_s[e] <= P.tau * lref;
+        if (acc && q != 0) atomicOr(&accw_s[q >> 6], 1ull << (q & 63));
+      }
+      wsync();
+      if (lane == 0) {
+        P.accept[2 * (int64_t)ck] = accw_s[0];
+        P.accept[2 * (int64_t)ck + 1] = accw_s[1];
+      }
       wsync();
     }
   }
