@@ -11,9 +11,11 @@ p50/p99 build latency, the FP64 roofline fraction of the weights kernel and
 the CPU oracle's rate on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -23,6 +25,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (256 CUs x 2.4 GHz x 128)
+HBM_PEAK_GBS = 8000.0
+
+# The weights kernel's HBM traffic comes from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs summarised in this file, together with the SHA-256 of the
+# kernel sources they were taken on; a stale summary reports null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "weights_reg_ball1M_traffic.md")
+KERNEL_SOURCES = ["paper_1606_03135_amd/csrc/weights_reg.hip",
+                  "paper_1606_03135_amd/csrc/weights_common.hpp"]
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the weights kernel, or None if the summary is
+    missing or was taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^- (\w+): `?([0-9a-f.e+]+)`?\s*$", text, re.M))
+    if fields.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def lu_flops(K, p):
@@ -52,11 +87,16 @@ def cpu_baseline(n, m, l, delta, n_sample):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--N", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
+                    help="nodes of the ball the oracle builds (default: the "
+                         "whole workload)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run a plain device copy of "
+                         "known size (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
@@ -139,10 +179,19 @@ def main():
         "roofline": {"bound": "alu", "kernel": "weights_reg_kernel<9,2>",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(),
                      "flops_per_launch": flops_launch,
                      "launch_ms": wk_ms},
     }
+    if args.copy_calibration:
+        # plain elementwise copy: reads and writes COPY_BYTES each
+        a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = COPY_BYTES
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, m, l, delta, args.cpu_sample)
     print(json.dumps(out), flush=True)

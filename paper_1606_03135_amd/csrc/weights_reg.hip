@@ -75,7 +75,9 @@ __device__ __forceinline__ double recip(double x) {
   return y;
 }
 
-template <int L, int PL>
+// ACC: acceptance mode (the stencil's ball nodes plus the reference node are
+// the columns; Lambda and the accept bits are written instead of W)
+template <int L, int PL, bool ACC>
 __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
   constexpr int LC = L + PL;
   constexpr int S = 8 * L;  // row / column slots of A_hat
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
       if (d == 3) nrm[2] = P.normals[ci * d + 2];
     }
     int ncol = 0, nball = 0;
-    const bool accept_mode = P.accept != nullptr;
+    constexpr bool accept_mode = ACC;
     if (accept_mode) {
       // columns: the center, its ball, and the stencil node nearest the
       // stencil centroid (Sec. 4.2.1), found exactly as the sequential
@@ -431,11 +433,15 @@ bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid) {
   if (P.M > 35) return false;
   const size_t dyn = ((size_t)(P.n + 8 * 2) * P.M + (size_t)3 * P.n * (P.l + 1)) *
                      sizeof(double);
-#define ORBF_REG_CASE(LL, PP)                                               \
-  if (P.K <= 8 * LL) {                                                      \
-    hipLaunchKernelGGL((weights_reg_kernel<LL, PP>), dim3((unsigned)grid),   \
-                       dim3(64), dyn, ctx->stream, P);                      \
-    return true;                                                            \
+#define ORBF_REG_CASE(LL, PP)                                                \
+  if (P.K <= 8 * LL) {                                                       \
+    if (P.accept)                                                            \
+      hipLaunchKernelGGL((weights_reg_kernel<LL, PP, true>),                 \
+                         dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P); \
+    else                                                                     \
+      hipLaunchKernelGGL((weights_reg_kernel<LL, PP, false>),                \
+                         dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P); \
+    return true;                                                             \
   }
   ORBF_REG_CASE(3, 2)
   ORBF_REG_CASE(4, 2)
