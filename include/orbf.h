@@ -63,9 +63,13 @@ typedef enum orbf_op {
 
 typedef enum orbf_prec {
   ORBF_PREC_FP64 = 0,   /* factor and solve in FP64                          */
-  ORBF_PREC_FP32_IR = 1 /* factor and solve in FP32, residuals and the
-                           Lebesgue test in FP64, iterative refinement with a
-                           per-stencil FP64 fallback                          */
+  ORBF_PREC_FP32_IR = 1 /* elimination and its replays in FP32; residuals
+                           B_hat - A_hat X, the accumulated solution X, the
+                           weights and the Lebesgue sums in FP64; refinement
+                           until max|dX| <= 1e-11 max|X| over the weights of
+                           every column (at most 8 corrections), stencils
+                           that do not settle solved again in FP64.  The
+                           covering decisions of mode (c) use FP64 solves.   */
 } orbf_prec;
 
 typedef struct orbf_ctx orbf_ctx;
@@ -161,8 +165,14 @@ typedef struct orbf_weights_args {
   double* W;             /* N*n output: W[e*n + q] is the weight of node
                             knn[owner[e]*n + q] in row e (physical units)    */
   double* lebesgue;      /* N output or NULL: Lambda of each computed row    */
-  int32_t* ir_steps;     /* N output or NULL (FP32_IR): refinement steps of
-                            the row's stencil, -1 if it fell back to FP64    */
+  int32_t* ir_steps;     /* N output or NULL, written when prec is FP32_IR
+                            in modes (b)/(c): the number of FP64-residual
+                            corrections after the first FP32 solve of the
+                            row's right-hand-side block; -1 where the row was
+                            solved in FP64 (FP32 zero pivot, no convergence
+                            within 8 corrections, n + M > 72, no owner).
+                            Mode (a) rows are always FP64 and leave it
+                            untouched.                                       */
 } orbf_weights_args;
 
 /* Local weights (Sec. 4.1, eqs. rbffd_linsys, orbffd_eq, orbffd_rhs).

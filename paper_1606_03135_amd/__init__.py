@@ -267,9 +267,14 @@ def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
         owner = torch.empty(N, dtype=torch.int32, device=xyz.device)
         p = None
     lam = torch.zeros(xyz.shape[0], dtype=torch.float64, device=xyz.device)
+    ir_steps = None
+    if prec == PREC_FP32_IR:
+        ir_steps = torch.empty(xyz.shape[0], dtype=torch.int32,
+                               device=xyz.device)
     W = compute_weights(ctx, OP_LAPLACIAN, m, l, n, delta, xyz, knn, rho2,
                         centers=centers, n_centers=n_centers, owner=owner,
-                        eligible=eligible, tau=tau, prec=prec, lebesgue=lam)
+                        eligible=eligible, tau=tau, prec=prec, lebesgue=lam,
+                        ir_steps=ir_steps)
     if boundary is not None and len(boundary):
         compute_weights(ctx, OP_NEUMANN, m, l, n, 1.0, xyz, knn, rho2,
                         rows=boundary, normals=normals, owner=owner, W=W,
@@ -279,4 +284,4 @@ def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
         ctx.sync()
     return dict(knn=knn, rho2=rho2, centers=centers, n_centers=n_centers,
                 owner=owner, p=p, W=W, lam=lam, row_ptr=row_ptr, col=col,
-                val=val, ctx=ctx)
+                val=val, ir_steps=ir_steps, ctx=ctx)

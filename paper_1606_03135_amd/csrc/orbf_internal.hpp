@@ -97,6 +97,8 @@ enum BufId {
   B_W_TMP,
   B_MISC,
   B_MISC2,
+  B_IR_FALLBACK,
+  B_IR_COUNT,
 };
 
 // ctx helpers (api.hip)

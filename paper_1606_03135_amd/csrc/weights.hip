@@ -334,6 +334,9 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   P.ball = nullptr;
   P.accept = nullptr;
   P.tau = a->tau;
+  P.ir_steps = nullptr;
+  P.fb_list = nullptr;
+  P.fb_count = nullptr;
   P.st = ctx->status;
   P.d = d;
   P.n = n;
@@ -353,12 +356,43 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   const int64_t work = explicit_rows ? a->n_rows : a->N;
   const int64_t grid = work < (int64_t)ctx->num_cus * 64 ? work : (int64_t)ctx->num_cus * 64;
   if (grid <= 0) return ORBF_OK;
-  hipEventRecord(ctx->ev[8], ctx->stream);
   static const bool force_lds = getenv("ORBF_WEIGHTS_LDS") != nullptr;
-  if (force_lds || !launch_weights_reg(ctx, P, grid))
-    hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
-                       lds_bytes(pcap), ctx->stream, P);
-  hipEventRecord(ctx->ev[9], ctx->stream);
+  // FP32 + refinement for covered rows; explicit rows, and systems beyond
+  // the register variants, are solved in FP64 (their ir_steps stay -1)
+  const bool use_ir = a->prec == ORBF_PREC_FP32_IR && !explicit_rows;
+  int32_t* fb_list = nullptr;
+  int64_t* fb_count = nullptr;
+  if (use_ir) {
+    fb_list = (int32_t*)scratch(ctx, B_IR_FALLBACK, (size_t)a->N * 4, &st);
+    if (st) return st;
+    fb_count = (int64_t*)scratch(ctx, B_IR_COUNT, 8, &st);
+    if (st) return st;
+    launch_ir_prepare(ctx, a->ir_steps, a->N, fb_count);
+  }
+  hipEventRecord(ctx->ev[8], ctx->stream);
+  bool ir_done = false;
+  if (use_ir && !force_lds) {
+    WeightsParams Q = P;
+    Q.ir_steps = a->ir_steps;
+    Q.fb_list = fb_list;
+    Q.fb_count = fb_count;
+    ir_done = launch_weights_ir(ctx, Q, grid);
+  }
+  if (ir_done) {
+    hipEventRecord(ctx->ev[9], ctx->stream);
+    // stencils the refinement did not settle: FP64 from scratch
+    WeightsParams F = P;
+    F.centers = fb_list;
+    F.n_centers = fb_count;
+    if (!launch_weights_reg(ctx, F, grid))
+      hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
+                         lds_bytes(pcap), ctx->stream, F);
+  } else {
+    if (force_lds || !launch_weights_reg(ctx, P, grid))
+      hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
+                         lds_bytes(pcap), ctx->stream, P);
+    hipEventRecord(ctx->ev[9], ctx->stream);
+  }
   ctx->phase_valid[4] = true;
   return hip_check(ctx, hipGetLastError(), "weights");
 }

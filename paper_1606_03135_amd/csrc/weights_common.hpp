@@ -5,6 +5,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "orbf_internal.hpp"
 
 namespace orbf {
@@ -29,6 +31,11 @@ struct WeightsParams {
   const uint64_t* ball;     // 2 words per node: ball positions q (j > c)
   uint64_t* accept;         // 2 words per node: accepted positions q
   double tau;
+  // FP32 + refinement: steps per row (or null), and the list of centers the
+  // FP64 kernel must solve again (with its device counter)
+  int32_t* ir_steps;
+  int32_t* fb_list;
+  int64_t* fb_count;
   DevStatus* st;
   int d, n, m, l, M, K, op, pcap, ldm;
 };
@@ -139,7 +146,53 @@ __device__ __forceinline__ double monomial_op_pw(const double* pw, int l1,
   return s;
 }
 
+// ---- wavefront helpers shared by the register-resident kernels ----
+
+// compile-time loop: f(integral_constant<B>), ..., f(integral_constant<E-1>)
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) {
+  return a > b ? a : b;
+}
+
+// max of a 32-bit key over each aligned group of 8 lanes (DPP, no LDS)
+__device__ __forceinline__ uint32_t group8_max(uint32_t k) {
+  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0xB1, 0xF, 0xF, false));
+  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0x4E, 0xF, 0xF, false));
+  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0x141, 0xF, 0xF, false));
+  return k;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// reciprocal of a wave-uniform value: hardware estimate + 2 Newton steps
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+
 bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid);
+bool launch_weights_ir(orbf_ctx* ctx, const WeightsParams& P, int64_t grid);
+void launch_ir_prepare(orbf_ctx* ctx, int32_t* ir_steps, int64_t N,
+                       int64_t* fb_count);
 orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
                                   double t2, const uint8_t* eligible,
                                   int32_t* centers, int64_t* n_centers,

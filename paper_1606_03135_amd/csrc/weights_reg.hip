@@ -26,54 +26,12 @@
 // Padded slots (>= K) are inactive from the start and hold zeros.
 #include <math.h>
 
-#include <type_traits>
-
 #include "orbf_internal.hpp"
 #include "weights_common.hpp"
 
 namespace orbf {
 
 namespace {
-
-template <int B, int E, class F>
-__device__ __forceinline__ void sfor(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    sfor<B + 1, E>(f);
-  }
-}
-
-__device__ __forceinline__ void wsync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) {
-  return a > b ? a : b;
-}
-
-// max of a 32-bit key over each aligned group of 8 lanes (DPP, no LDS)
-__device__ __forceinline__ uint32_t group8_max(uint32_t k) {
-  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0xB1, 0xF, 0xF, false));
-  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0x4E, 0xF, 0xF, false));
-  k = umax(k, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k, 0x141, 0xF, 0xF, false));
-  return k;
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
-
-// reciprocal of a wave-uniform value: hardware estimate + 2 Newton steps
-__device__ __forceinline__ double recip(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = fma(fma(-x, y, 1.0), y, y);
-  y = fma(fma(-x, y, 1.0), y, y);
-  return y;
-}
 
 // ACC: acceptance mode (the stencil's ball nodes plus the reference node are
 // the columns; Lambda and the accept bits are written instead of W)

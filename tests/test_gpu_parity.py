@@ -231,3 +231,72 @@ def test_bitwise_repeatable(orbf, ctx):
     b = orbf.build_dm(gpu(x), 50, 5, 3, 0.3, ctx=ctx)
     for key in ("knn", "rho2", "owner", "W", "col", "val"):
         assert torch.equal(a[key], b[key]), key
+
+
+IR_CASES = ["square45_d05", "square45_d1", "disk5k_d05", "ball20k_d03",
+            "ball1237_d0", "disk5k_d03_tau1"]
+
+
+@pytest.mark.parametrize("case", IR_CASES)
+def test_fp32_refined_matches_oracle(orbf, ctx, case):
+    """FP32 elimination + FP64 refinement: same covering and CSR structure,
+    weights within the FP64 bar."""
+    x, el, bnd, nrm, c = make(case)
+    tau = c.get("tau", math.inf)
+    _say(f"[gpu] fp32+ir {case} N={len(x)}")
+    ref = oracle.build_dm(x, c["n"], c["m"], c["l"], c["delta"], tau=tau,
+                          eligible=el, boundary=bnd, normals=nrm)
+    got = orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"], tau=tau,
+                        eligible=None if el is None else gpu(el),
+                        boundary=None if bnd is None else gpu(bnd),
+                        normals=None if nrm is None else gpu(nrm),
+                        prec=orbf.PREC_FP32_IR, ctx=ctx)
+    owner = got["owner"].cpu().numpy()
+    assert np.array_equal(got["knn"].cpu().numpy(), ref["knn"])
+    assert np.array_equal(owner, ref["owner"])
+    assert np.array_equal(got["col"].cpu().numpy(), ref["col"])
+    rows = owner >= 0
+    err = row_err(got["W"].cpu().numpy()[rows], ref["W"][rows])
+    steps = got["ir_steps"].cpu().numpy()
+    interior = rows.copy()
+    if bnd is not None:
+        interior[bnd] = False
+        assert (steps[bnd] == -1).all()  # boundary rows are FP64
+    st = steps[interior]
+    settled = st >= 0
+    _say(f"[gpu] fp32+ir {case}: max row rel err {err:.2e}, corrections "
+         f"max {st.max()} mean {st[settled].mean():.2f}, FP64 fallback "
+         f"{(~settled).mean():.4f}")
+    assert err <= TOL
+    assert st.min() >= -1 and st.max() <= 8
+    assert settled.mean() > 0.9
+
+
+def test_fp32_refined_ball_full_size(orbf, ctx):
+    """1M-node ball: FP32 + refinement against the FP64 GPU build (every
+    row) and against the oracle on sampled rows."""
+    x = nodesets.ball(1_000_000, 2)["x"]
+    n, m, l, delta = 50, 5, 3, 0.3
+    _say("[gpu] ball 1M fp32+ir build")
+    xd = gpu(x)
+    a = orbf.build_dm(xd, n, m, l, delta, ctx=ctx)
+    b = orbf.build_dm(xd, n, m, l, delta, prec=orbf.PREC_FP32_IR, ctx=ctx)
+    assert torch.equal(a["owner"], b["owner"])
+    assert torch.equal(a["col"], b["col"])
+    Wa, Wb = a["W"], b["W"]
+    rel = ((Wa - Wb).abs().amax(1) / Wa.abs().amax(1)).max().item()
+    steps = b["ir_steps"].cpu().numpy()
+    settled = steps >= 0
+    _say(f"[gpu] ball 1M fp32+ir vs fp64: max row rel diff {rel:.2e}; "
+         f"corrections mean {steps[settled].mean():.2f} max {steps.max()}; "
+         f"FP64 fallback {(~settled).mean():.5f}")
+    assert rel <= TOL
+    W = Wb.cpu().numpy()
+    owner = b["owner"].cpu().numpy()
+    knn = b["knn"].cpu().numpy()
+    worst = 0.0
+    for e in np.random.default_rng(1).choice(len(x), 200, False):
+        w = oracle.stencil_weights(x[knn[owner[e]]], x[e][None, :], m, l)[0]
+        worst = max(worst, np.abs(W[e] - w).max() / np.abs(w).max())
+    _say(f"[gpu] ball 1M fp32+ir: sampled oracle max row rel err {worst:.2e}")
+    assert worst <= TOL
