@@ -207,6 +207,136 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
  * last launch.  Valid after orbf_sync. */
 orbf_status orbf_phase_times(orbf_ctx* ctx, double* ms5 /* host, 5 */);
 
+/* ------------------------------------------------------------------------
+ * Batched builds: many independent node sets in one call.
+ * ---------------------------------------------------------------------- */
+
+/* One node set of a batch: inputs, parameters and caller-allocated device
+ * outputs (the arrays of the single-set calls above, same layouts).  Every
+ * set gets the whole path: stencils, covering (with the Lebesgue test when
+ * tau is finite), Laplacian rows at the eligible nodes, normal-derivative
+ * rows at the boundary nodes, CSR. */
+typedef struct orbf_set_desc {
+  const double* xyz;        /* N*d coordinates                               */
+  int64_t N;
+  int d;                    /* 2 or 3                                        */
+  int n;                    /* stencil size                                  */
+  int m;                    /* odd PHS exponent >= 3                         */
+  int l;                    /* polynomial degree                             */
+  double delta;             /* overlap parameter in [0,1]                    */
+  double tau;               /* Lebesgue threshold, INFINITY = off            */
+  orbf_prec prec;
+  const uint8_t* eligible;  /* N or NULL = every node gets a Laplacian row   */
+  const int32_t* boundary;  /* n_boundary nodes with normal-derivative rows,
+                               or NULL                                      */
+  int64_t n_boundary;
+  const double* normals;    /* n_boundary*d unit normals                     */
+  int32_t* knn;             /* outputs: N*n                                  */
+  double* rho2;             /* N                                             */
+  int32_t* centers;         /* N (capacity)                                  */
+  int64_t* n_centers;       /* 1                                             */
+  int32_t* owner;           /* N                                             */
+  double* W;                /* N*n                                           */
+  double* lebesgue;         /* N or NULL                                     */
+  int32_t* ir_steps;        /* N or NULL                                     */
+  int64_t* row_ptr;         /* N+1                                           */
+  int32_t* col;             /* N*n                                           */
+  double* val;              /* N*n                                           */
+} orbf_set_desc;
+
+/* Build the DMs of `nsets` node sets.  The sets are dealt to the context's
+ * worker streams (each with its own scratch), largest estimated cost first
+ * to the least-loaded worker, and joined back onto the context's stream; the
+ * call is asynchronous like the others.  A batch whose descriptors are
+ * byte-identical to the previous call's is captured into a HIP graph on its
+ * second occurrence and replayed from the third on (only when every set has
+ * tau = INFINITY, whose path has no host round trip).  A set's results do
+ * not depend on the other sets of the batch.
+ * Errors: EINVAL naming the first bad set; device errors at orbf_sync. */
+orbf_status orbf_build_dm_batched(orbf_ctx* ctx, const orbf_set_desc* sets,
+                                  int nsets);
+
+/* Number of worker streams for batched builds (1..16, default 4).  Each
+ * worker holds its own scratch within the context's HBM budget divided by
+ * the number of workers. */
+orbf_status orbf_set_workers(orbf_ctx* ctx, int workers);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request engine with continuous admission.
+ * ---------------------------------------------------------------------- */
+
+/* A server owns `slots` streams (each with its own scratch) and one arena of
+ * device memory that holds the outputs of admitted requests.  Requests wait
+ * in FIFO order; a request is admitted when a slot is free and its outputs
+ * fit in the arena (first fit); a later, smaller request may pass a waiting
+ * head at most 8 times before the head blocks admission.  Admitted requests
+ * run concurrently on their slots; results stay on the device until
+ * released.  Progress is driven by orbf_server_poll (no hidden threads).
+ * A finished request keeps its arena memory until orbf_server_release: a
+ * caller that holds every result until all requests are done can stall
+ * admission once the arena is full of finished results.
+ * Device memory held: arena_bytes + slots * slot_scratch_bytes. */
+typedef struct orbf_server orbf_server;
+
+typedef struct orbf_request {
+  const double* xyz;   /* N*d device coordinates, caller-owned; must stay
+                          valid until the request is done                   */
+  int64_t N;
+  int d, n, m, l;
+  double delta;
+  double tau;          /* INFINITY = off                                     */
+  orbf_prec prec;
+  double t_arrival;    /* arrival time on the orbf_server_now clock          */
+} orbf_request;
+
+typedef struct orbf_result {
+  int status;          /* orbf_status of the build (device errors included)  */
+  int64_t N;
+  int n;
+  int64_t n_centers;   /* number of stencils                                 */
+  double t_arrival;    /* seconds, orbf_server_now clock                     */
+  double t_admit;      /* admitted to a slot                                 */
+  double t_done;       /* completion observed by orbf_server_poll            */
+} orbf_result;
+
+orbf_status orbf_server_create(int device, int slots, size_t arena_bytes,
+                               size_t slot_scratch_bytes, orbf_server** out);
+void orbf_server_destroy(orbf_server* srv);  /* waits for running requests   */
+const char* orbf_server_last_error(const orbf_server* srv);
+double orbf_server_now(void);  /* steady clock, seconds                      */
+
+/* Device bytes a request's outputs take in the arena. */
+size_t orbf_request_bytes(int64_t N, int d, int n, orbf_prec prec);
+
+/* Queue a request; *ticket identifies it.  EINVAL for bad parameters,
+ * EBUDGET if it could never fit (outputs larger than the arena, or
+ * orbf_workspace_size larger than slot_scratch_bytes). */
+orbf_status orbf_server_submit(orbf_server* srv, const orbf_request* req,
+                               uint64_t* ticket);
+
+/* Retire finished requests and admit waiting ones.  Writes up to `cap`
+ * tickets finished since the previous call to done[] (host array) and their
+ * number to *n_done. */
+orbf_status orbf_server_poll(orbf_server* srv, uint64_t* done, int cap,
+                             int* n_done);
+
+/* Status and timing of a finished request (EINVAL if unknown or not done). */
+orbf_status orbf_server_result(orbf_server* srv, uint64_t ticket,
+                               orbf_result* out);
+
+/* Copy a finished request's outputs into caller device buffers: the output
+ * fields of `dst` (knn, rho2, centers, n_centers, owner, W, lebesgue,
+ * ir_steps, row_ptr, col, val; NULL fields are skipped). Synchronous. */
+orbf_status orbf_server_fetch(orbf_server* srv, uint64_t ticket,
+                              const orbf_set_desc* dst);
+
+/* Free a finished request's arena memory; its ticket becomes unknown. */
+orbf_status orbf_server_release(orbf_server* srv, uint64_t ticket);
+
+/* [0] waiting, [1] running, [2] finished and not released, [3] arena bytes
+ * in use, [4] arena bytes in total. */
+orbf_status orbf_server_stats(orbf_server* srv, int64_t out5[5]);
+
 #ifdef __cplusplus
 }
 #endif

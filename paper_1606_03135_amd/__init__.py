@@ -56,6 +56,27 @@ class WeightsArgs(ctypes.Structure):
                 ("W", _P), ("lebesgue", _P), ("ir_steps", _P)]
 
 
+class SetDesc(ctypes.Structure):
+    _fields_ = [("xyz", _P), ("N", _I64), ("d", _I), ("n", _I), ("m", _I),
+                ("l", _I), ("delta", _D), ("tau", _D), ("prec", _I),
+                ("eligible", _P), ("boundary", _P), ("n_boundary", _I64),
+                ("normals", _P), ("knn", _P), ("rho2", _P), ("centers", _P),
+                ("n_centers", _P), ("owner", _P), ("W", _P),
+                ("lebesgue", _P), ("ir_steps", _P), ("row_ptr", _P),
+                ("col", _P), ("val", _P)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("xyz", _P), ("N", _I64), ("d", _I), ("n", _I), ("m", _I),
+                ("l", _I), ("delta", _D), ("tau", _D), ("prec", _I),
+                ("t_arrival", _D)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", _I), ("N", _I64), ("n", _I), ("n_centers", _I64),
+                ("t_arrival", _D), ("t_admit", _D), ("t_done", _D)]
+
+
 _lib = None
 
 
@@ -90,6 +111,37 @@ def lib():
         L.orbf_assemble_csr.restype = _I
         L.orbf_phase_times.argtypes = [_P, ctypes.POINTER(_D)]
         L.orbf_phase_times.restype = _I
+        L.orbf_build_dm_batched.argtypes = [_P, ctypes.POINTER(SetDesc), _I]
+        L.orbf_build_dm_batched.restype = _I
+        L.orbf_set_workers.argtypes = [_P, _I]
+        L.orbf_set_workers.restype = _I
+        L.orbf_server_create.argtypes = [_I, _I, ctypes.c_size_t,
+                                         ctypes.c_size_t, _P]
+        L.orbf_server_create.restype = _I
+        L.orbf_server_destroy.argtypes = [_P]
+        L.orbf_server_destroy.restype = None
+        L.orbf_server_last_error.argtypes = [_P]
+        L.orbf_server_last_error.restype = ctypes.c_char_p
+        L.orbf_server_now.argtypes = []
+        L.orbf_server_now.restype = _D
+        L.orbf_request_bytes.argtypes = [_I64, _I, _I, _I]
+        L.orbf_request_bytes.restype = ctypes.c_size_t
+        L.orbf_server_submit.argtypes = [_P, ctypes.POINTER(Request),
+                                         ctypes.POINTER(ctypes.c_uint64)]
+        L.orbf_server_submit.restype = _I
+        L.orbf_server_poll.argtypes = [_P, ctypes.POINTER(ctypes.c_uint64),
+                                       _I, ctypes.POINTER(_I)]
+        L.orbf_server_poll.restype = _I
+        L.orbf_server_result.argtypes = [_P, ctypes.c_uint64,
+                                         ctypes.POINTER(Result)]
+        L.orbf_server_result.restype = _I
+        L.orbf_server_fetch.argtypes = [_P, ctypes.c_uint64,
+                                        ctypes.POINTER(SetDesc)]
+        L.orbf_server_fetch.restype = _I
+        L.orbf_server_release.argtypes = [_P, ctypes.c_uint64]
+        L.orbf_server_release.restype = _I
+        L.orbf_server_stats.argtypes = [_P, ctypes.POINTER(_I64)]
+        L.orbf_server_stats.restype = _I
         _lib = L
     return _lib
 
@@ -285,3 +337,162 @@ def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
     return dict(knn=knn, rho2=rho2, centers=centers, n_centers=n_centers,
                 owner=owner, p=p, W=W, lam=lam, row_ptr=row_ptr, col=col,
                 val=val, ir_steps=ir_steps, ctx=ctx)
+
+
+def _outputs(N, n, dev, prec):
+    """Device output tensors of one DM build."""
+    o = dict(knn=torch.empty((N, n), dtype=torch.int32, device=dev),
+             rho2=torch.empty(N, dtype=torch.float64, device=dev),
+             centers=torch.empty(N, dtype=torch.int32, device=dev),
+             n_centers=torch.zeros(1, dtype=torch.int64, device=dev),
+             owner=torch.empty(N, dtype=torch.int32, device=dev),
+             W=torch.empty((N, n), dtype=torch.float64, device=dev),
+             lam=torch.zeros(N, dtype=torch.float64, device=dev),
+             ir_steps=None,
+             row_ptr=torch.empty(N + 1, dtype=torch.int64, device=dev),
+             col=torch.empty(N * n, dtype=torch.int32, device=dev),
+             val=torch.empty(N * n, dtype=torch.float64, device=dev))
+    if prec == PREC_FP32_IR:
+        o["ir_steps"] = torch.empty(N, dtype=torch.int32, device=dev)
+    return o
+
+
+def _fill_outputs(dsc, o):
+    dsc.knn, dsc.rho2 = _ptr(o["knn"]), _ptr(o["rho2"])
+    dsc.centers, dsc.n_centers = _ptr(o["centers"]), _ptr(o["n_centers"])
+    dsc.owner, dsc.W, dsc.lebesgue = (_ptr(o["owner"]), _ptr(o["W"]),
+                                      _ptr(o["lam"]))
+    dsc.ir_steps = _ptr(o["ir_steps"])
+    dsc.row_ptr, dsc.col, dsc.val = (_ptr(o["row_ptr"]), _ptr(o["col"]),
+                                     _ptr(o["val"]))
+
+
+def build_dm_batched(ctx, sets, outputs=None, sync=True):
+    """Many DM builds in one call (``orbf_build_dm_batched``).
+
+    ``sets``: list of dicts with ``xyz`` (device float64 [N, d]), ``n``,
+    ``m``, ``l``, ``delta`` and optionally ``tau``, ``prec``, ``eligible``,
+    ``boundary``, ``normals``.  ``outputs``: the list this function returned
+    before, to build into the same buffers (a repeated batch with the same
+    buffers is replayed from a HIP graph).  Returns one dict of device
+    tensors per set."""
+    descs = (SetDesc * len(sets))()
+    keep = []
+    if outputs is None:
+        outputs = []
+        for s in sets:
+            x = s["xyz"]
+            outputs.append(_outputs(x.shape[0], s["n"], x.device,
+                                    s.get("prec", PREC_FP64)))
+    for i, s in enumerate(sets):
+        x = _dev(s["xyz"], torch.float64, "xyz")
+        dsc = descs[i]
+        dsc.xyz, dsc.N, dsc.d = _ptr(x), x.shape[0], x.shape[1]
+        dsc.n, dsc.m, dsc.l = int(s["n"]), int(s["m"]), int(s["l"])
+        dsc.delta = float(s["delta"])
+        dsc.tau = float(s.get("tau", math.inf))
+        dsc.prec = int(s.get("prec", PREC_FP64))
+        if s.get("eligible") is not None:
+            el = _dev(s["eligible"], torch.uint8, "eligible")
+            keep.append(el)
+            dsc.eligible = _ptr(el)
+        if s.get("boundary") is not None:
+            b = _dev(s["boundary"], torch.int32, "boundary")
+            nr = _dev(s["normals"], torch.float64, "normals")
+            keep += [b, nr]
+            dsc.boundary, dsc.n_boundary, dsc.normals = (_ptr(b), b.numel(),
+                                                         _ptr(nr))
+        keep.append(x)
+        _fill_outputs(dsc, outputs[i])
+    ctx.check(lib().orbf_build_dm_batched(ctx._h, descs, len(sets)))
+    if sync:
+        ctx.sync()
+    ctx._batch_keep = keep  # inputs stay alive while the batch may run
+    return outputs
+
+
+class Server:
+    """Request engine with continuous admission (``orbf_server_*``).
+
+    ``slots`` concurrent builds; ``arena`` bytes of device memory for the
+    outputs of admitted requests; ``slot_scratch`` bytes of scratch per
+    slot (a request needs orbf_workspace_size of it)."""
+
+    def __init__(self, device=0, slots=4, arena=6 << 30,
+                 slot_scratch=512 << 20):
+        L = lib()
+        h = ctypes.c_void_p()
+        rc = L.orbf_server_create(int(device), int(slots), int(arena),
+                                  int(slot_scratch), ctypes.byref(h))
+        if rc != OK:
+            raise OrbfError(rc, "orbf_server_create failed")
+        self._h = h
+        self.device = device
+        self._inputs = {}
+
+    def check(self, rc):
+        if rc != OK:
+            raise OrbfError(rc, lib().orbf_server_last_error(self._h).decode())
+
+    @staticmethod
+    def now():
+        return lib().orbf_server_now()
+
+    def submit(self, xyz, n, m, l, delta, tau=math.inf, prec=PREC_FP64,
+               t_arrival=None):
+        x = _dev(xyz, torch.float64, "xyz")
+        r = Request(xyz=_ptr(x), N=x.shape[0], d=x.shape[1], n=int(n),
+                    m=int(m), l=int(l), delta=float(delta), tau=float(tau),
+                    prec=int(prec),
+                    t_arrival=self.now() if t_arrival is None else t_arrival)
+        t = ctypes.c_uint64()
+        self.check(lib().orbf_server_submit(self._h, ctypes.byref(r),
+                                            ctypes.byref(t)))
+        self._inputs[t.value] = x  # the request reads it until done
+        return t.value
+
+    def poll(self, cap=1024):
+        buf = (ctypes.c_uint64 * cap)()
+        k = _I()
+        self.check(lib().orbf_server_poll(self._h, buf, cap, ctypes.byref(k)))
+        return [buf[i] for i in range(k.value)]
+
+    def result(self, ticket):
+        r = Result()
+        self.check(lib().orbf_server_result(self._h, ticket, ctypes.byref(r)))
+        return dict(status=r.status, N=r.N, n=r.n, n_centers=r.n_centers,
+                    t_arrival=r.t_arrival, t_admit=r.t_admit,
+                    t_done=r.t_done)
+
+    def fetch(self, ticket, prec=PREC_FP64):
+        """Copy a finished request's outputs into new device tensors."""
+        info = self.result(ticket)
+        o = _outputs(info["N"], info["n"], torch.device("cuda", self.device),
+                     prec)
+        dsc = SetDesc()
+        _fill_outputs(dsc, o)
+        self.check(lib().orbf_server_fetch(self._h, ticket,
+                                           ctypes.byref(dsc)))
+        return o
+
+    def release(self, ticket):
+        self.check(lib().orbf_server_release(self._h, ticket))
+        self._inputs.pop(ticket, None)
+
+    def stats(self):
+        a = (_I64 * 5)()
+        self.check(lib().orbf_server_stats(self._h, a))
+        return dict(waiting=a[0], running=a[1], finished=a[2],
+                    arena_used=a[3], arena_bytes=a[4])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().orbf_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -95,9 +95,10 @@ struct PhaseTimer {
   orbf_ctx* ctx;
   int slot;
   PhaseTimer(orbf_ctx* c, int s) : ctx(c), slot(s) {
-    hipEventRecord(ctx->ev[2 * s], ctx->stream);
+    if (ctx->timing) hipEventRecord(ctx->ev[2 * s], ctx->stream);
   }
   ~PhaseTimer() {
+    if (!ctx->timing) return;
     hipEventRecord(ctx->ev[2 * slot + 1], ctx->stream);
     ctx->phase_valid[slot] = true;
   }
@@ -136,12 +137,18 @@ void orbf_destroy(orbf_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  for (orbf_ctx* w : ctx->workers) orbf_destroy(w);
+  for (hipEvent_t e : ctx->join_ev) hipEventDestroy(e);
+  if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
+  drop_graph(ctx);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   for (auto& b : ctx->buf)
     if (b.ptr) hipFree(b.ptr);
   if (ctx->status) hipFree(ctx->status);
   if (ctx->status_host) hipHostFree(ctx->status_host);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);
+  if (ctx->owns_stream && ctx->stream) hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -157,6 +164,14 @@ orbf_status orbf_sync(orbf_ctx* ctx) {
                                 ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_check(ctx, e, "sync");
+  // batched builds: the workers' status words (their streams joined ours)
+  for (orbf_ctx* w : ctx->workers) {
+    const orbf_status ws = orbf_sync(w);
+    if (ws != ORBF_OK) {
+      ctx->err = "batch worker: " + w->err;
+      return ws;
+    }
+  }
   const DevStatus s = *ctx->status_host;
   if (s.code == 0) return ORBF_OK;
   hipMemsetAsync(ctx->status, 0, sizeof(DevStatus), ctx->stream);
@@ -171,15 +186,32 @@ orbf_status orbf_sync(orbf_ctx* ctx) {
 size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   (void)l;
   (void)prec;
-  if (N < 1 || n < 1) return 0;
+  if (N < 1 || n < 1 || (d != 2 && d != 3)) return 0;
+  // Every scratch buffer is grow-only and rounded up by scratch(); the sum
+  // over buffer ids of the largest request each id sees in a build bounds
+  // what a context holds (kNN, covering with or without the Lebesgue test,
+  // weights in either precision, CSR).
+  auto want = [](size_t b) { return (b ? b : 8) + (b ? b : 8) / 8 + 256; };
   const size_t Nn = (size_t)N;
-  // grid: cell ids, ranks, counts, starts, permutation, sorted coordinates
-  size_t knn = Nn * 4 * 3 + (Nn + 66) * 8 + Nn * 4 + Nn * (size_t)d * 8;
-  // covering: masks, degrees, starts, fill, state, flags, positions, list,
-  // predecessor lists (bounded by N (n-1))
-  size_t cover = Nn * 16 + Nn * 4 * 5 + Nn * 8 * 2 + Nn * (size_t)(n - 1) * 4;
-  size_t scan = (Nn / 1024 + 64) * 16 + 256;
-  return (knn > cover ? knn : cover) + knn / 4 + scan + (1 << 20);
+  const size_t edges = Nn * (size_t)(n > 1 ? n - 1 : 1);
+  size_t t = 0;
+  t += want(sizeof(GridParams));        // B_GRID_PARAMS
+  t += want(1024 * 6 * 8);              // B_PARTIAL
+  t += want(Nn * 4) * 2;                // B_CELL_OF, B_CELL_RANK
+  t += want((Nn + 65) * 4);             // B_FLAGS (cell counts, flags)
+  t += want((Nn + 66) * 8);             // B_CELL_START
+  t += want(Nn * 4);                    // B_PERM
+  t += want(Nn * (size_t)d * 8);        // B_XS
+  t += want(Nn * 16);                   // B_BALL
+  t += want((Nn + 1) * 4) * 3;          // B_INDEG, B_PRED_FILL, B_ROWPTR_TMP
+  t += want((Nn + 2) * 8) * 2;          // B_PRED_START, B_CENTER_POS
+  t += want(Nn * 4);                    // B_STATE
+  t += want(edges * 4);                 // B_PRED
+  t += want(Nn * 16);                   // B_W_TMP (Lebesgue covering)
+  t += want(64);                        // B_MISC2
+  t += want(scan_tmp_elems((int64_t)Nn + 66) * 8);  // B_SCAN_TMP
+  t += want(Nn * 4) + want(8);          // B_IR_FALLBACK, B_IR_COUNT
+  return t;
 }
 
 orbf_status orbf_build_nodes_knn(orbf_ctx* ctx, const double* xyz, int64_t N,

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "orbf.h"
 
@@ -68,6 +69,19 @@ struct orbf_ctx {
   orbf::Buffer buf[32];
   int num_cus = 256;
   hipEvent_t ev[10] = {};
+  bool timing = true;  // record phase events (off on batch/serving workers)
+  bool owns_stream = false;  // created by the library (workers, slots)
+  bool is_worker = false;
+  // batched builds: worker contexts, fork/join events, graph of the last
+  // repeated batch (key = its descriptors and worker count)
+  int n_workers = 4;
+  std::vector<orbf_ctx*> workers;
+  std::vector<hipEvent_t> join_ev;
+  hipEvent_t fork_ev = nullptr;
+  hipStream_t cap_stream = nullptr;  // origin of graph capture
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<unsigned char> graph_key;
+  int graph_seen = 0;
   float phase_ms[5] = {0, 0, 0, 0, 0};
   bool phase_valid[5] = {false, false, false, false, false};
   int32_t* host_counter = nullptr;  // pinned, covering round control
@@ -110,6 +124,7 @@ orbf_status hip_check(orbf_ctx* ctx, hipError_t e, const char* what);
 // int64 output; temp from scratch (scan.hip)
 orbf_status exclusive_scan_i32_to_i64(orbf_ctx* ctx, const int32_t* in,
                                       int64_t n, int64_t* out);
+size_t scan_tmp_elems(int64_t n);  // int64 temporaries of a scan of n
 
 // phase launchers
 orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
@@ -123,5 +138,10 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
 orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        const int32_t* owner, const double* W,
                        int64_t* row_ptr, int32_t* col, double* val);
+
+// batched builds and serving (batch.hip)
+orbf_status build_set(orbf_ctx* c, const orbf_set_desc& s);
+orbf_status ensure_workers(orbf_ctx* ctx, int want);
+void drop_graph(orbf_ctx* ctx);
 
 }  // namespace orbf

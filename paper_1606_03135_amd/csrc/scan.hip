@@ -85,6 +85,8 @@ orbf_status scan_level(orbf_ctx* ctx, const T* in, int64_t n, int64_t* out,
   return hip_check(ctx, hipGetLastError(), "scan");
 }
 
+}  // namespace
+
 size_t scan_tmp_elems(int64_t n) {
   size_t total = 16;
   while (n > 0) {
@@ -95,8 +97,6 @@ size_t scan_tmp_elems(int64_t n) {
   }
   return total;
 }
-
-}  // namespace
 
 orbf_status exclusive_scan_i32_to_i64(orbf_ctx* ctx, const int32_t* in,
                                       int64_t n, int64_t* out) {

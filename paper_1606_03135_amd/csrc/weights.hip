@@ -271,7 +271,7 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
                            double t2, const orbf_weights_args* a) {
   orbf_status st = ORBF_OK;
   const int d = a->d;
-  int8_t ex[3 * 512];
+  int8_t ex[3 * 512] = {};
   int M = 0;
   for (int deg = 0; deg <= l; ++deg) {
     if (d == 2) {
@@ -292,11 +292,8 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
     }
   }
   const int K = n + M;
-  auto* dex = (int8_t*)scratch(ctx, B_MISC, 3 * (size_t)M, &st);
-  if (st) return st;
-  hipError_t e = hipMemcpyAsync(dex, ex, 3 * (size_t)M, hipMemcpyHostToDevice,
-                                ctx->stream);
-  if ((st = hip_check(ctx, e, "weights: exponent upload"))) return st;
+  if (M > 80) return fail(ctx, ORBF_EINVAL, "compute_weights: M > 80");
+  hipError_t e = hipSuccess;
 
   int max_lds = 65536;
   hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
@@ -328,7 +325,7 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   P.N = a->N;
   P.owner_out = explicit_rows ? a->owner : nullptr;
   P.normals = a->normals;
-  P.ex = dex;
+  for (int t = 0; t < 3 * 80; ++t) P.ex[t] = t < 3 * M ? ex[t] : 0;
   P.W = a->W;
   P.lebesgue = a->lebesgue;
   P.ball = nullptr;
@@ -369,7 +366,7 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
     if (st) return st;
     launch_ir_prepare(ctx, a->ir_steps, a->N, fb_count);
   }
-  hipEventRecord(ctx->ev[8], ctx->stream);
+  if (ctx->timing) hipEventRecord(ctx->ev[8], ctx->stream);
   bool ir_done = false;
   if (use_ir && !force_lds) {
     WeightsParams Q = P;
@@ -379,7 +376,7 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
     ir_done = launch_weights_ir(ctx, Q, grid);
   }
   if (ir_done) {
-    hipEventRecord(ctx->ev[9], ctx->stream);
+    if (ctx->timing) hipEventRecord(ctx->ev[9], ctx->stream);
     // stencils the refinement did not settle: FP64 from scratch
     WeightsParams F = P;
     F.centers = fb_list;
@@ -391,9 +388,9 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
     if (force_lds || !launch_weights_reg(ctx, P, grid))
       hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
                          lds_bytes(pcap), ctx->stream, P);
-    hipEventRecord(ctx->ev[9], ctx->stream);
+    if (ctx->timing) hipEventRecord(ctx->ev[9], ctx->stream);
   }
-  ctx->phase_valid[4] = true;
+  ctx->phase_valid[4] = ctx->timing;
   return hip_check(ctx, hipGetLastError(), "weights");
 }
 

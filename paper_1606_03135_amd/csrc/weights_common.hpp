@@ -23,7 +23,10 @@ struct WeightsParams {
   int64_t N;
   int32_t* owner_out;       // explicit rows: owner[row] = row
   const double* normals;    // explicit rows, NEUMANN: n_rows * d
-  const int8_t* ex;         // M * 3 monomial exponents, graded lex
+  // M * 3 monomial exponents, graded lex, passed by value (no host copy
+  // on the stream, so a build can be captured in a graph); M <= 80 since
+  // n >= M and n + M <= 160
+  int8_t ex[3 * 80];
   double* W;                // N * n
   double* lebesgue;         // N or null
   // acceptance mode (Lebesgue covering): solve the ball columns of each

@@ -1,0 +1,242 @@
+"""Batched builds and the request engine, through the C ABI.
+
+Every set or request runs the single-set kernels on a worker stream of its
+own, so its outputs must equal, bit for bit, those of a single-set build of
+the same input (and therefore the oracle's to the usual bars); graph replays
+of a repeated batch must equal the eager run; a request's result must not
+depend on what else is in flight.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import nodesets
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+KEYS = ("knn", "rho2", "owner", "W", "row_ptr", "col", "val")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def orbf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1606_03135_amd as P
+    P.lib()
+    return P
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def small_specs(count, seed, nmax=12000):
+    """Batch descriptions of the batched workload's kind, sizes capped so
+    the oracle and single-set builds stay quick."""
+    out = []
+    for s in nodesets.batch_specs(count, seed):
+        s = dict(s)
+        if s["N"] > nmax:
+            s["N"] = nmax if s["d"] == 3 else int(math.sqrt(nmax)) ** 2
+        out.append(s)
+    return out
+
+
+def as_set(spec, x, prec=0):
+    return dict(xyz=gpu(x), n=spec["n"], m=spec["m"], l=spec["l"],
+                delta=spec["delta"], prec=prec)
+
+
+def same(a, b, keys=KEYS):
+    for k in keys:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_batched_equals_single_and_oracle(orbf):
+    ctx = orbf.Context(0)
+    specs = small_specs(24, 4)
+    xs = [nodesets.make_set(s) for s in specs]
+    sets = [as_set(s, x) for s, x in zip(specs, xs)]
+    # one disk set with boundary rows and the Lebesgue test
+    D = nodesets.disk(3000, 120, 1)
+    sets.append(dict(xyz=gpu(D["x"]), n=31, m=5, l=4, delta=0.5, tau=5.0,
+                     eligible=gpu(D["eligible"]), boundary=gpu(D["boundary"]),
+                     normals=gpu(D["normals"])))
+    _say(f"[gpu] batched {len(sets)} sets, N total "
+         f"{sum(s['xyz'].shape[0] for s in sets)}")
+    outs = orbf.build_dm_batched(ctx, sets)
+    for i, (s, o) in enumerate(zip(sets, outs)):
+        r = orbf.build_dm(s["xyz"], s["n"], s["m"], s["l"], s["delta"],
+                          tau=s.get("tau", math.inf),
+                          eligible=s.get("eligible"),
+                          boundary=s.get("boundary"),
+                          normals=s.get("normals"), ctx=ctx)
+        same(o, r)
+        assert int(o["n_centers"].item()) == int(r["n_centers"].item())
+    # the oracle on a few sets (bit-exact structure, 1e-9 weights)
+    for i in (0, 5, 11, len(sets) - 1):
+        s = sets[i]
+        x = s["xyz"].cpu().numpy()
+        el = s.get("eligible")
+        ref = oracle.build_dm(
+            x, s["n"], s["m"], s["l"], s["delta"], tau=s.get("tau", math.inf),
+            eligible=None if el is None else el.cpu().numpy(),
+            boundary=None if s.get("boundary") is None
+            else s["boundary"].cpu().numpy(),
+            normals=None if s.get("normals") is None
+            else s["normals"].cpu().numpy())
+        o = outs[i]
+        assert np.array_equal(o["knn"].cpu().numpy(), ref["knn"])
+        assert np.array_equal(o["owner"].cpu().numpy(), ref["owner"])
+        assert np.array_equal(o["col"].cpu().numpy(), ref["col"])
+        own = ref["owner"] >= 0
+        W = o["W"].cpu().numpy()[own]
+        err = float((np.abs(W - ref["W"][own]).max(1) /
+                     np.abs(ref["W"][own]).max(1)).max())
+        _say(f"[gpu] batched set {i}: N={len(x)} d={x.shape[1]} "
+             f"max row rel err {err:.2e}")
+        assert err <= 1e-9
+
+
+def test_batched_graph_replay(orbf):
+    """The second identical call is captured, later ones replayed; every
+    call must reproduce the eager result, with eager work in between."""
+    ctx = orbf.Context(0)
+    specs = small_specs(16, 7)
+    sets = [as_set(s, nodesets.make_set(s)) for s in specs]
+    outs = orbf.build_dm_batched(ctx, sets)
+    ref = [{k: o[k].clone() for k in KEYS} for o in outs]
+    for rep in range(4):
+        for o in outs:
+            for k in KEYS:
+                o[k].zero_()
+        torch.cuda.synchronize()
+        orbf.build_dm_batched(ctx, sets, outputs=outs)
+        _say(f"[gpu] graph replay {rep}")
+        for o, r in zip(outs, ref):
+            same(o, r)
+
+
+def test_batched_fp32_refined(orbf):
+    ctx = orbf.Context(0)
+    specs = small_specs(12, 9)
+    xs = [nodesets.make_set(s) for s in specs]
+    a = orbf.build_dm_batched(ctx, [as_set(s, x) for s, x in zip(specs, xs)])
+    b = orbf.build_dm_batched(ctx, [as_set(s, x, orbf.PREC_FP32_IR)
+                                    for s, x in zip(specs, xs)])
+    worst = 0.0
+    for oa, ob in zip(a, b):
+        assert torch.equal(oa["owner"], ob["owner"])
+        assert torch.equal(oa["col"], ob["col"])
+        rel = ((oa["W"] - ob["W"]).abs().amax(1) /
+               oa["W"].abs().amax(1)).max().item()
+        worst = max(worst, rel)
+    _say(f"[gpu] batched fp32+ir vs fp64: max row rel diff {worst:.2e}")
+    assert worst <= 1e-9
+
+
+def _drain(srv, tickets, timeout_s=120.0):
+    done = set()
+    t0 = srv.now()
+    while len(done) < len(tickets):
+        done.update(srv.poll())
+        assert srv.now() - t0 < timeout_s, "server did not finish"
+    return done
+
+
+def test_server_alone_equals_mix(orbf):
+    """A request's outputs are the same alone and among others in flight,
+    and equal a single-set build."""
+    ctx = orbf.Context(0)
+    specs = [dict(s, t=0.0) for s in small_specs(10, 11, nmax=30000)]
+    xs = [gpu(nodesets.make_set(s)) for s in specs]
+    probe = 3
+    srv = orbf.Server(0, slots=4, arena=3 << 30, slot_scratch=256 << 20)
+    t = srv.submit(xs[probe], specs[probe]["n"], specs[probe]["m"],
+                   specs[probe]["l"], specs[probe]["delta"])
+    _drain(srv, [t])
+    alone = srv.fetch(t)
+    assert srv.result(t)["status"] == 0
+    srv.release(t)
+    tickets = [srv.submit(x, s["n"], s["m"], s["l"], s["delta"])
+               for s, x in zip(specs, xs)]
+    _say(f"[gpu] server mix of {len(tickets)}: {srv.stats()}")
+    _drain(srv, tickets)
+    mixed = srv.fetch(tickets[probe])
+    same(mixed, alone)
+    for s, x, t in zip(specs, xs, tickets):
+        info = srv.result(t)
+        assert info["status"] == 0
+        assert info["t_arrival"] <= info["t_admit"] <= info["t_done"]
+        r = orbf.build_dm(x, s["n"], s["m"], s["l"], s["delta"], ctx=ctx)
+        same(srv.fetch(t), r)
+        assert info["n_centers"] == int(r["n_centers"].item())
+        srv.release(t)
+    assert srv.stats()["arena_used"] == 0
+    srv.close()
+
+
+def test_server_budget_admission(orbf):
+    """With an arena that holds about two requests at a time, requests wait
+    for memory, the head is passed a bounded number of times, and every
+    result is still right."""
+    specs = [dict(s) for s in small_specs(8, 13, nmax=20000)]
+    xs = [gpu(nodesets.make_set(s)) for s in specs]
+    L = orbf.lib()
+    need = max(L.orbf_request_bytes(x.shape[0], x.shape[1], s["n"], 0)
+               for s, x in zip(specs, xs))
+    ws = max(L.orbf_workspace_size(x.shape[0], x.shape[1], s["n"], s["l"], 0)
+             for s, x in zip(specs, xs))
+    arena = int(need * 2.3)  # the largest request fits, three do not
+    ctx = orbf.Context(0)
+    refs = [orbf.build_dm(x, s["n"], s["m"], s["l"], s["delta"], ctx=ctx)
+            for s, x in zip(specs, xs)]
+    srv = orbf.Server(0, slots=4, arena=arena, slot_scratch=ws)
+    tickets = [srv.submit(x, s["n"], s["m"], s["l"], s["delta"])
+               for s, x in zip(specs, xs)]
+    index = {t: i for i, t in enumerate(tickets)}
+    # a finished request holds its arena memory until released, so results
+    # are consumed as they come
+    done, waited = set(), 0
+    t0 = srv.now()
+    while len(done) < len(tickets):
+        assert srv.now() - t0 < 60.0, f"stalled: {srv.stats()}"
+        fin = srv.poll()
+        st = srv.stats()
+        assert st["arena_used"] <= st["arena_bytes"]
+        waited = max(waited, st["waiting"])
+        for t in fin:
+            assert srv.result(t)["status"] == 0
+            same(srv.fetch(t), refs[index[t]])
+            srv.release(t)
+            done.add(t)
+    _say(f"[gpu] arena {arena >> 20} MiB: max waiting {waited}")
+    assert waited > 0
+    assert srv.stats()["arena_used"] == 0
+    srv.close()
+
+
+def test_server_and_batch_errors(orbf):
+    srv = orbf.Server(0, slots=2, arena=48 << 20, slot_scratch=16 << 20)
+    x = gpu(np.random.default_rng(0).random((500, 2)))
+    with pytest.raises(orbf.OrbfError) as e:
+        srv.submit(x, 8, 4, 2, 0.5)  # even PHS exponent
+    assert e.value.code == orbf.EINVAL
+    big = gpu(np.random.default_rng(1).random((400000, 3)))
+    with pytest.raises(orbf.OrbfError) as e:
+        srv.submit(big, 50, 5, 3, 0.3)  # outputs larger than the arena
+    assert e.value.code == orbf.EBUDGET
+    srv.close()
+    ctx = orbf.Context(0)
+    with pytest.raises(orbf.OrbfError) as e:
+        orbf.build_dm_batched(ctx, [dict(xyz=x, n=8, m=3, l=2, delta=1.5)])
+    assert e.value.code == orbf.EINVAL

@@ -300,3 +300,24 @@ def test_fp32_refined_ball_full_size(orbf, ctx):
         worst = max(worst, np.abs(W[e] - w).max() / np.abs(w).max())
     _say(f"[gpu] ball 1M fp32+ir: sampled oracle max row rel err {worst:.2e}")
     assert worst <= TOL
+
+
+@pytest.mark.parametrize("case", ["disk5k_d03_tau1", "ball20k_d03",
+                                  "square45_d1"])
+def test_workspace_size_bounds_scratch(orbf, case):
+    """A context capped at orbf_workspace_size completes a build (either
+    precision, finite tau, boundary rows); half of it is refused."""
+    x, el, bnd, nrm, c = make(case)
+    tau = c.get("tau", math.inf)
+    for prec in (orbf.PREC_FP64, orbf.PREC_FP32_IR):
+        ws = orbf.workspace_size(len(x), x.shape[1], c["n"], c["l"], prec)
+        _say(f"[gpu] workspace {case} prec {prec}: {ws} bytes")
+        kw = dict(tau=tau, eligible=None if el is None else gpu(el),
+                  boundary=None if bnd is None else gpu(bnd),
+                  normals=None if nrm is None else gpu(nrm), prec=prec)
+        orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"],
+                      ctx=orbf.Context(0, budget=ws), **kw)
+        with pytest.raises(orbf.OrbfError) as e:
+            orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"],
+                          ctx=orbf.Context(0, budget=ws // 2), **kw)
+        assert e.value.code == orbf.EBUDGET
