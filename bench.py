@@ -1,14 +1,23 @@
 """Benchmark: overlapped RBF-FD differentiation-matrix build on one MI355X.
 
-One step = one whole DM build from device-resident nodes to device-resident
-CSR: stencils (kNN), greedy overlapped covering, per-stencil saddle solves,
-CSR scatter.  Workload: 3D unit ball, N = 1,000,000 nodes (scrambled Halton
-interior + Fibonacci shell), PHS r^5, polynomial degree 3 (M = 20), stencil
-n = 50, delta = 0.3, Laplacian at every node, FP64.
+Default workload (the headline): one step = one whole DM build from
+device-resident nodes to device-resident CSR (stencils, greedy overlapped
+covering, per-stencil saddle solves, CSR) of the 3D unit ball with
+N = 1,000,000 nodes (scrambled Halton interior + Fibonacci shell), PHS r^5,
+polynomial degree 3 (M = 20), stencil n = 50, delta = 0.3, Laplacian at
+every node, FP64.  Prints one JSON line: weights/s (nnz / build time),
+stencils/s, phase times, p50/p99 build latency, the FP64 roofline fraction
+of the weights kernel, the FP32 + FP64-refinement variant of the same build
+with its weight error, and the CPU oracle's rate on the same workload.
 
-Prints one JSON line: weights/s (nnz / build time), stencils/s, phase times,
-p50/p99 build latency, the FP64 roofline fraction of the weights kernel and
-the CPU oracle's rate on a bounded sample of the same workload.
+--workload batched: 512 mixed node sets (N log-uniform in [1e3, 2e5], 2D/3D,
+l in {2,3,4}, n in [2M+1, 3M], delta in {0.2, 0.5, 1}) in one batched call,
+FP32 + refinement (and FP64 beside it); repeated batches replay a HIP graph.
+
+--workload serving: Poisson stream of DM-build requests (N lognormal,
+median 2e4, clipped to [5e3, 5e5]; 2D/3D; l in {2,3,4}; delta ~ U[0.2, 1];
+n = 2M+1) into the request engine; saturation throughput mu from a closed
+loop, then open-loop runs at 0.5 mu and 0.8 mu with p50/p99 latency.
 """
 import argparse
 import hashlib
@@ -84,30 +93,18 @@ def cpu_baseline(n, m, l, delta, n_sample):
                        f"nodes, same n/m/l/delta: {dt:.2f} s, nnz={nnz}")}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--N", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
-                    help="nodes of the ball the oracle builds (default: the "
-                         "whole workload)")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the timed steps, run a plain device copy of "
-                         "known size (to scale HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU "
-              "path (run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    import torch
 
-    import nodesets
-    import paper_1606_03135_amd as orbf
+def build_flops(r, K):
+    nc = int(r["n_centers"].item())
+    p = np.bincount(r["owner"].cpu().numpy().clip(0))[
+        r["centers"][:nc].cpu().numpy()].astype(np.float64)
+    return float(np.sum(lu_flops(K, p))), nc
 
+
+def bench_ball(args, torch, orbf, nodesets):
     n, m, l, delta = 50, 5, 3, 0.3
     M = math.comb(l + 3, 3)
     K = n + M
@@ -117,30 +114,31 @@ def main():
     xd = torch.from_numpy(x).to(dev)
     ctx = orbf.Context(0)
 
-    def step():
-        return orbf.build_dm(xd, n, m, l, delta, ctx=ctx, sync=True)
+    def run(prec, steps, warmup):
+        def step():
+            return orbf.build_dm(xd, n, m, l, delta, ctx=ctx, sync=True,
+                                 prec=prec)
+        r = None
+        for _ in range(max(warmup, 1)):
+            r = step()
+        torch.cuda.synchronize()
+        lat, wk, phases = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            r = step()
+            lat.append(time.perf_counter() - s0)
+            pt = ctx.phase_times()
+            phases.append(pt[:4])
+            wk.append(pt[4])
+        torch.cuda.synchronize()
+        return r, lat, wk, phases, time.perf_counter() - t0
 
-    for _ in range(args.warmup):
-        r = step()
-    r = step() if args.warmup == 0 else r
-    nc = int(r["n_centers"].item())
-    p = r["p"][:nc].cpu().numpy().astype(np.float64)
-    flops_launch = float(np.sum(lu_flops(K, p)))
+    r, lat, wk, phases, elapsed = run(orbf.PREC_FP64, args.steps,
+                                      args.warmup)
+    _log(f"FP64: {1e3 * elapsed / args.steps:.2f} ms per build")
+    flops_launch, nc = build_flops(r, K)
     nnz = int(r["row_ptr"][-1].item())
-
-    torch.cuda.synchronize()
-    lat, wk, phases = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        step()
-        lat.append(time.perf_counter() - s0)
-        pt = ctx.phase_times()
-        phases.append(pt[:4])
-        wk.append(pt[4])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
     ms_step = 1e3 * elapsed / args.steps
     value = nnz * args.steps / elapsed
     wk_ms = float(np.mean(wk))
@@ -176,13 +174,31 @@ def main():
                      "csr": ph[3]},
         "hbm_gbs": {"knn": knn_bytes / (ph[0] * 1e-3) / 1e9,
                     "csr": csr_bytes / (ph[3] * 1e-3) / 1e9},
-        "roofline": {"bound": "alu", "kernel": "weights_reg_kernel<9,2>",
+        "roofline": {"bound": "alu", "kernel": "weights_reg_kernel<9,2,false>",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(),
                      "flops_per_launch": flops_launch,
                      "launch_ms": wk_ms},
     }
+    if not args.no_fp32:
+        W64 = r["W"].clone()
+        steps32 = max(3, args.steps // 5)
+        r32, lat32, wk32, _, el32 = run(orbf.PREC_FP32_IR, steps32, 1)
+        rel = ((W64 - r32["W"]).abs().amax(1) /
+               W64.abs().amax(1)).max().item()
+        st = r32["ir_steps"].cpu().numpy()
+        ok = st >= 0
+        out["fp32_ir"] = {
+            "value": nnz * steps32 / el32, "unit": "weights/s",
+            "steps": steps32, "ms_per_step": 1e3 * el32 / steps32,
+            "weights_kernel_ms": float(np.mean(wk32)),
+            "achieved_tflops": flops_launch / (np.mean(wk32) * 1e-3) / 1e12,
+            "max_row_rel_err_vs_fp64": rel,
+            "corrections_mean": float(st[ok].mean()) if ok.any() else None,
+            "corrections_max": int(st.max()),
+            "fp64_fallback_rows": float((~ok).mean())}
+        del W64, r32
     if args.copy_calibration:
         # plain elementwise copy: reads and writes COPY_BYTES each
         a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev)
@@ -194,7 +210,184 @@ def main():
         out["copy_calibration_bytes"] = COPY_BYTES
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, m, l, delta, args.cpu_sample)
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_batched(args, torch, orbf, nodesets):
+    specs = nodesets.batch_specs(args.sets, 4)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    xs = [torch.from_numpy(nodesets.make_set(s)).to(dev) for s in specs]
+    gen_s = time.perf_counter() - t0
+    _log(f"{len(specs)} node sets generated in {gen_s:.1f} s")
+    ctx = orbf.Context(0)
+
+    def sets_for(prec):
+        return [dict(xyz=x, n=s["n"], m=s["m"], l=s["l"], delta=s["delta"],
+                     prec=prec) for s, x in zip(specs, xs)]
+
+    def run(prec, steps, warmup):
+        sets = sets_for(prec)
+        outs = orbf.build_dm_batched(ctx, sets)
+        _log(f"prec {prec}: first batch done")
+        for _ in range(max(warmup, 2)):  # second call captures the graph
+            orbf.build_dm_batched(ctx, sets, outputs=outs)
+        _log(f"prec {prec}: warm-up done")
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            orbf.build_dm_batched(ctx, sets, outputs=outs)
+            lat.append(time.perf_counter() - s0)
+        torch.cuda.synchronize()
+        return outs, lat, time.perf_counter() - t0
+
+    o32, lat32, el32 = run(orbf.PREC_FP32_IR, args.steps, args.warmup)
+    nnz = sum(int(o["row_ptr"][-1].item()) for o in o32)
+    ncent = sum(int(o["n_centers"].item()) for o in o32)
+    W32 = [o["W"].clone() for o in o32]
+    st = np.concatenate([o["ir_steps"].cpu().numpy() for o in o32])
+    del o32
+    o64, lat64, el64 = run(orbf.PREC_FP64, args.steps, args.warmup)
+    rel = max(((a["W"] - b).abs().amax(1) / a["W"].abs().amax(1)).max().item()
+              for a, b in zip(o64, W32))
+    ok = st >= 0
+    Ks = [s["n"] + s["M"] for s in specs]
+    return {
+        "metric": "RBF-FD weights/sec, batched DM build of 512 mixed node "
+                  "sets (FP32 LU + FP64 refinement)",
+        "value": nnz * args.steps / el32, "unit": "weights/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el32 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64ir",
+        "data": "synthetic",
+        "config": {"workload": f"{len(specs)} node sets, N log-uniform "
+                               f"[1e3, 2e5] (sum {sum(x.shape[0] for x in xs)}"
+                               f"), 2D jittered grids / 3D balls, l in "
+                               f"{{2,3,4}}, n in [2M+1, 3M], delta in "
+                               f"{{0.2,0.5,1.0}}, Laplacian",
+                   "K_range": [min(Ks), max(Ks)], "workers": 4,
+                   "parallelism": "single GPU"},
+        "nnz": nnz, "n_centers": ncent,
+        "stencils_per_s": ncent * args.steps / el32,
+        "fp64": {"value": nnz * args.steps / el64, "unit": "weights/s",
+                 "ms_per_step": 1e3 * el64 / args.steps},
+        "max_row_rel_err_vs_fp64": rel,
+        "corrections_mean": float(st[ok].mean()) if ok.any() else None,
+        "fp64_rows": float((~ok).mean()),
+        "node_generation_s": gen_s,
+    }
+
+
+def bench_serving(args, torch, orbf, nodesets):
+    dev = torch.device("cuda:0")
+    pool = nodesets.request_specs(args.pool, 1.0, 5)
+    t0 = time.perf_counter()
+    xs = [torch.from_numpy(nodesets.make_set(s)).to(dev) for s in pool]
+    gen_s = time.perf_counter() - t0
+    _log(f"{len(pool)} node sets generated in {gen_s:.1f} s")
+    rng = np.random.Generator(np.random.PCG64(6))
+    arena = max(orbf.lib().orbf_request_bytes(x.shape[0], x.shape[1],
+                                              s["n"], 0)
+                for s, x in zip(pool, xs)) * 4 * args.slots
+    scratch = max(orbf.workspace_size(x.shape[0], x.shape[1], s["n"], s["l"])
+                  for s, x in zip(pool, xs))
+    srv = orbf.Server(0, slots=args.slots, arena=arena, slot_scratch=scratch)
+
+    def run(count, rate):
+        """rate None: closed loop (all arrive at once)."""
+        picks = rng.integers(0, len(pool), count)
+        gaps = (rng.exponential(1.0 / rate, count) if rate
+                else np.zeros(count))
+        arrive = np.cumsum(gaps)
+        lat, nnz = [], 0
+        start = srv.now() + 0.01
+        i = done = 0
+        while done < count:
+            now = srv.now()
+            while i < count and start + arrive[i] <= now:
+                k = picks[i]
+                s = pool[k]
+                srv.submit(xs[k], s["n"], s["m"], s["l"], s["delta"],
+                           t_arrival=start + arrive[i])
+                i += 1
+            for t in srv.poll():
+                info = srv.result(t)
+                assert info["status"] == 0, info
+                lat.append(info["t_done"] - info["t_arrival"])
+                nnz += info["N"] * info["n"]
+                srv.release(t)
+                done += 1
+        span = srv.now() - start
+        _log(f"{count} requests at rate {rate}: {count / span:.1f} req/s")
+        lat = np.array(lat)
+        return {"requests": count,
+                "offered_rps": rate, "achieved_rps": count / span,
+                "weights_per_s": nnz / span,
+                "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                "p99_ms": 1e3 * float(np.percentile(lat, 99))}
+
+    run(min(64, args.requests), None)  # warm-up (scratch, code objects)
+    sat = run(args.requests, None)
+    mu = sat["achieved_rps"]
+    loads = {"saturation": sat}
+    for f in (0.5, 0.8):
+        loads[f"{f}mu"] = run(args.requests, f * mu)
+    srv.close()
+    main_load = loads["0.5mu"]
+    return {
+        "metric": "DM-build serving: p50/p99 request latency and weights/s "
+                  "under Poisson arrivals",
+        "value": main_load["weights_per_s"], "unit": "weights/s",
+        "n_gpus": 1, "steps": args.requests, "warmup": 64,
+        "ms_per_step": 1e3 / main_load["achieved_rps"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"Poisson stream, {args.pool} distinct node "
+                               f"sets (N lognormal median 2e4 sigma 1, "
+                               f"clipped [5e3, 5e5], 2D/3D, l in {{2,3,4}}, "
+                               f"delta U[0.2,1], n=2M+1), {args.slots} slots",
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": main_load["p50_ms"], "p99": main_load["p99_ms"]},
+        "loads": loads, "node_generation_s": gen_s,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ball",
+                    choices=["ball", "batched", "serving"])
+    ap.add_argument("--N", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
+                    help="nodes of the ball the oracle builds (default: the "
+                         "whole workload)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--sets", type=int, default=512)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--pool", type=int, default=128)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run a plain device copy of "
+                         "known size (to scale HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU "
+              "path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import nodesets
+    import paper_1606_03135_amd as orbf
+
+    fn = {"ball": bench_ball, "batched": bench_batched,
+          "serving": bench_serving}[args.workload]
+    print(json.dumps(fn(args, torch, orbf, nodesets)), flush=True)
 
 
 if __name__ == "__main__":

@@ -54,6 +54,18 @@ void* scratch(orbf_ctx* ctx, int id, size_t bytes, orbf_status* st) {
   return b.ptr;
 }
 
+// Free every scratch buffer of an idle context (hipFree waits for the
+// device).  Grow-only buffers keep the largest size each id has seen over
+// many builds, which can exceed what any one build needs.
+void release_scratch(orbf_ctx* ctx) {
+  for (auto& b : ctx->buf) {
+    if (b.ptr) hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  ctx->held = 0;
+}
+
 static int num_monomials(int d, int l) {
   long num = 1, den = 1;
   for (int i = 1; i <= d; ++i) {

@@ -462,6 +462,11 @@ void start(orbf_server* s, int si, uint64_t id) {
   q.state = RUNNING;
   q.slot = si;
   q.t_admit = now_s();
+  // the slot's grow-only scratch holds the largest buffers of earlier
+  // requests; start from nothing if keeping them could pass the cap
+  const size_t need =
+      orbf_workspace_size(q.r.N, q.r.d, q.r.n, q.r.l, q.r.prec);
+  if (sl.ctx->held + need > s->slot_budget) release_scratch(sl.ctx);
   const orbf_set_desc d = desc_of(s, q);
   orbf_status st = build_set(sl.ctx, d);
   if (st) q.status = st;

@@ -118,6 +118,7 @@ enum BufId {
 // ctx helpers (api.hip)
 orbf_status fail(orbf_ctx* ctx, orbf_status code, const std::string& msg);
 void* scratch(orbf_ctx* ctx, int id, size_t bytes, orbf_status* st);
+void release_scratch(orbf_ctx* ctx);
 orbf_status hip_check(orbf_ctx* ctx, hipError_t e, const char* what);
 
 // exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total),
