@@ -354,6 +354,14 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   const int64_t grid = work < (int64_t)ctx->num_cus * 64 ? work : (int64_t)ctx->num_cus * 64;
   if (grid <= 0) return ORBF_OK;
   static const bool force_lds = getenv("ORBF_WEIGHTS_LDS") != nullptr;
+  // FP64 kernels by size: one wavefront (K <= 72), one workgroup of four
+  // (K <= 144), else the LDS-resident kernel
+  auto fp64 = [&](const WeightsParams& Q) {
+    if (launch_weights_reg(ctx, Q, grid)) return;
+    if (launch_weights_wg(ctx, Q, work)) return;
+    hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
+                       lds_bytes(pcap), ctx->stream, Q);
+  };
   // FP32 + refinement for covered rows; explicit rows, and systems beyond
   // the register variants, are solved in FP64 (their ir_steps stay -1)
   const bool use_ir = a->prec == ORBF_PREC_FP32_IR && !explicit_rows;
@@ -381,13 +389,13 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
     WeightsParams F = P;
     F.centers = fb_list;
     F.n_centers = fb_count;
-    if (!launch_weights_reg(ctx, F, grid))
-      hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
-                         lds_bytes(pcap), ctx->stream, F);
+    fp64(F);
   } else {
-    if (force_lds || !launch_weights_reg(ctx, P, grid))
+    if (force_lds)
       hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
                          lds_bytes(pcap), ctx->stream, P);
+    else
+      fp64(P);
     if (ctx->timing) hipEventRecord(ctx->ev[9], ctx->stream);
   }
   ctx->phase_valid[4] = ctx->timing;

@@ -63,6 +63,12 @@ CASES = {
                               tau=1.0),
     "ball20k_d03_tau2": dict(kind="ball", N=20000, n=50, m=5, l=3, delta=0.3,
                              tau=2.0),
+    # n + M > 72: the four-wavefront kernel
+    "ball3k_l4_n105": dict(kind="ball", N=3000, n=105, m=5, l=4, delta=0.5),
+    "ball3k_l4_n90_d1": dict(kind="ball", N=3000, n=90, m=5, l=4, delta=1.0),
+    "ball5k_l3_n60_d02": dict(kind="ball", N=5000, n=60, m=5, l=3,
+                              delta=0.2),
+    "disk5k_l4_n60": dict(kind="disk", N=5000, n=60, m=5, l=4, delta=0.5),
 }
 
 
