@@ -184,7 +184,7 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
         if (c == cc) {
           sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
             constexpr int ii = decltype(iic)::value;
-            lbuf[r * L + ii] = a[ii][kb];
+            lbuf[r * L + ii] = (ii == iip && r == rp) ? 0.0f : a[ii][kb];
           });
         }
         if (lane == 0) {
@@ -196,15 +196,19 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
         if (!(upiv != 0.0f)) zero_pivot = true;
         const float dk = zero_pivot ? 0.0f : __builtin_amdgcn_rcpf(upiv);
         if (lane == 0) dinv_s[k] = dk;
-        float u[L];
+        float u[L], lv[L];
         sfor<kb, L>([&](auto jjc) __attribute__((always_inline)) {
           constexpr int jj = decltype(jjc)::value;
           u[jj] = ubuf[c * L + jj];
         });
         sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
           constexpr int ii = decltype(iic)::value;
+          lv[ii] = lbuf[r * L + ii];
+        });
+        sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+          constexpr int ii = decltype(iic)::value;
           const bool is_piv = ii == iip && r == rp;
-          const float lm = is_piv ? 0.0f : lbuf[r * L + ii] * dk;
+          const float lm = lv[ii] * dk;
           // column block kb: columns right of k are updated, column k
           // receives the multiplier, columns left of k hold earlier ones
           const float upd = fmaf(-lm, u[kb], a[ii][kb]);
@@ -326,10 +330,12 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
             if (k >= K) break;
             const int piv = __builtin_amdgcn_readfirstlane(piv_s[k]);
             const int iip = piv >> 3, rp = piv & 7;
+            // stored multipliers of step k; the pivot row's slot holds
+            // u_kk, which the replay must not apply
             if (c == cc) {
               sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
                 constexpr int ii = decltype(iic)::value;
-                lbuf[r * L + ii] = a[ii][kb];
+                lbuf[r * L + ii] = (ii == iip && r == rp) ? 0.0f : a[ii][kb];
               });
             }
             sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
@@ -345,15 +351,18 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
               }
             });
             wsync();
-            float ur[PL];
+            float ur[PL], lv[L];
             sfor<0, PL>([&](auto jpc) __attribute__((always_inline)) {
               constexpr int jp = decltype(jpc)::value;
               ur[jp] = ubuf[c * PL + jp];
             });
             sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
               constexpr int ii = decltype(iic)::value;
-              const bool is_piv = ii == iip && r == rp;
-              const float lm = is_piv ? 0.0f : lbuf[r * L + ii];
+              lv[ii] = lbuf[r * L + ii];
+            });
+            sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+              constexpr int ii = decltype(iic)::value;
+              const float lm = lv[ii];
               sfor<0, PL>([&](auto jpc) __attribute__((always_inline)) {
                 constexpr int jp = decltype(jpc)::value;
                 rhs[ii][jp] = fmaf(-lm, ur[jp], rhs[ii][jp]);

@@ -279,10 +279,14 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
             constexpr int ii = decltype(iic)::value;
             act[ii] = (ii == iip && r == rp) ? 0u : act[ii];
           });
+          // the pivot value itself comes by readlane, so its reciprocal is
+          // under way while the LDS broadcast is in flight
+          double upiv = 0.0;
           sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
             constexpr int ii = decltype(iic)::value;
             if (iip == ii) {
               __asm__ volatile("; pivot row out %0" ::"i"(ii));
+              upiv = readlane_f64(a[ii][kb], 8 * cc + rp);
               if (r == rp) {
                 sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
                   constexpr int jj = decltype(jjc)::value;
@@ -291,30 +295,34 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
               }
             }
           });
+          // multipliers of column k; the pivot row's is written as zero, so
+          // the update below needs no per-row test
           if (c == cc) {
             sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
               constexpr int ii = decltype(iic)::value;
-              lbuf[r * L + ii] = a[ii][kb];
+              lbuf[r * L + ii] = (ii == iip && r == rp) ? 0.0 : a[ii][kb];
             });
           }
           if (lane == 0) srank[piv] = k;
-          wsync();
-          const double upiv = ubuf[cc * LC + kb];
           if (!(upiv != 0.0)) singular = true;
           const double dk = singular ? 0.0 : recip(upiv);
+          wsync();
           if (lane == 0) dinv[k] = dk;
           // 3. rank-1 update
-          double u[LC];
+          double u[LC], lv[L];
           sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
             constexpr int jj = decltype(jjc)::value;
             u[jj] = ubuf[c * LC + jj];
+          });
+          sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+            constexpr int ii = decltype(iic)::value;
+            lv[ii] = lbuf[r * L + ii];
           });
           // Gauss-Jordan: every row but the pivot row is eliminated, the
           // rows pivoted earlier included, so no back substitution follows
           sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
             constexpr int ii = decltype(iic)::value;
-            const bool is_piv = ii == iip && r == rp;
-            const double l = is_piv ? 0.0 : lbuf[r * L + ii] * dk;
+            const double l = lv[ii] * dk;
             sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
               constexpr int jj = decltype(jjc)::value;
               a[ii][jj] = fma(-l, u[jj], a[ii][jj]);

@@ -231,10 +231,11 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
               }
             }
           });
+          // multipliers of column k, the pivot row's written as zero
           if (c == cc) {
             sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
               constexpr int ii = decltype(iic)::value;
-              lbuf[r * L + ii] = a[ii][kb];
+              lbuf[r * L + ii] = (ii == iip && r == rp) ? 0.0 : a[ii][kb];
             });
           }
           if (t == 0) srank[piv] = k;
@@ -243,15 +244,18 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
           if (!(upiv != 0.0)) singular = true;
           const double dk = singular ? 0.0 : recip(upiv);
           if (t == 0) dinv[k] = dk;
-          double u[LC];
+          double u[LC], lv[L];
           sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
             constexpr int jj = decltype(jjc)::value;
             u[jj] = ubuf[c * LC + jj];
           });
           sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
             constexpr int ii = decltype(iic)::value;
-            const bool is_piv = ii == iip && r == rp;
-            const double lm = is_piv ? 0.0 : lbuf[r * L + ii] * dk;
+            lv[ii] = lbuf[r * L + ii];
+          });
+          sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+            constexpr int ii = decltype(iic)::value;
+            const double lm = lv[ii] * dk;
             sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
               constexpr int jj = decltype(jjc)::value;
               a[ii][jj] = fma(-lm, u[jj], a[ii][jj]);
