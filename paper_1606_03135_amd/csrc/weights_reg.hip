@@ -39,7 +39,7 @@ template <int L, int PL, bool ACC>
 __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
   constexpr int LC = L + PL;
   constexpr int S = 8 * L;  // row / column slots of A_hat
-  extern __shared__ double dyn_s[];  // psi (n x M) then L psi (8 PL x M)
+  extern __shared__ double dyn_s[];  // L psi (8 PL x M), then powers
   __shared__ double xi_s[3 * S];
   __shared__ int cols_s[S];
   __shared__ int8_t ex_s[3 * 36];
@@ -56,9 +56,11 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
   const int lane = threadIdx.x;
   const int r = lane & 7, c = lane >> 3;
   const int n = P.n, K = P.K, d = P.d, M = P.M, m = P.m, op = P.op;
-  double* psi_s = dyn_s;           // psi_t(xi_q), q < n, t < M
-  double* lpsi_s = dyn_s + n * M;  // L psi_t at the evaluation points
-  double* pw_s = lpsi_s + 8 * PL * M;  // powers of the scaled coordinates
+  // no table of psi_t(xi_q): monomials are formed from the power table
+  // during assembly, which keeps LDS per wavefront small enough for two
+  // wavefronts per SIMD
+  double* lpsi_s = dyn_s;               // L psi_t at the evaluation points
+  double* pw_s = lpsi_s + 8 * PL * M;   // powers of the scaled coordinates
   for (int t = lane; t < 3 * M; t += 64) ex_s[t] = P.ex[t];
 
   const bool explicit_rows = P.rows != nullptr;
@@ -180,11 +182,6 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         acc *= v;
       }
     }
-    wsync();
-    for (int t = lane; t < n * M; t += 64) {
-      const int q = t / M, s = t - q * M;
-      psi_s[t] = monomial_pw(pw_s + 3 * q * l1, l1, ex_s + 3 * s);
-    }
     const double sinv = 1.0 / ((op == ORBF_OP_LAPLACIAN) ? r2c : rho);
 
     for (int cb = 0; cb < ncol; cb += 8 * PL) {
@@ -218,9 +215,9 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
               const double dz = xi2 - xi_s[3 * j + 2];
               v = phs(dx * dx + dy * dy + dz * dz, m);
             } else if (i < n && j < K) {
-              v = psi_s[i * M + (j - n)];
+              v = monomial_pw(pw_s + 3 * i * l1, l1, ex_s + 3 * (j - n));
             } else if (j < n && i < K) {
-              v = psi_s[j * M + (i - n)];
+              v = monomial_pw(pw_s + 3 * j * l1, l1, ex_s + 3 * (i - n));
             }
           } else {
             const int e = 8 * (jj - L) + c;
@@ -397,8 +394,8 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
 // Launch the register kernel if a variant covers K; returns false otherwise.
 bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid) {
   if (P.M > 35) return false;
-  const size_t dyn = ((size_t)(P.n + 8 * 2) * P.M + (size_t)3 * P.n * (P.l + 1)) *
-                     sizeof(double);
+  const size_t dyn =
+      ((size_t)8 * 2 * P.M + (size_t)3 * P.n * (P.l + 1)) * sizeof(double);
 #define ORBF_REG_CASE(LL, PP)                                                \
   if (P.K <= 8 * LL) {                                                       \
     if (P.accept)                                                            \
