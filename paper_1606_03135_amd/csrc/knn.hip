@@ -30,6 +30,93 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ double readlane_f64_knn(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// (d, j) < (e, k) in the stencil order: squared distance, then index
+__device__ __forceinline__ bool key_less(double d, int j, double e, int k) {
+  return d < e || (d == e && j < k);
+}
+
+// One compare-exchange stage of a bitonic sort over the elements
+// i = lane + 64 h held in registers (d[h], j[h]); partners at i ^ STRIDE
+// (STRIDE < 64: another lane, same register).
+template <int SIZE, int STRIDE, int NR>
+__device__ __forceinline__ void bitonic_stage(double (&d)[NR], int (&j)[NR],
+                                              int lane) {
+#pragma unroll
+  for (int h = 0; h < NR; ++h) {
+    const int i = lane + 64 * h;
+    const double pd = __shfl_xor(d[h], STRIDE, 64);
+    const int pj = __shfl_xor(j[h], STRIDE, 64);
+    const bool keep_min = ((i & STRIDE) == 0) == ((i & SIZE) == 0);
+    const bool take = keep_min ? key_less(pd, pj, d[h], j[h])
+                               : key_less(d[h], j[h], pd, pj);
+    d[h] = take ? pd : d[h];
+    j[h] = take ? pj : j[h];
+  }
+}
+
+template <int SIZE, int STRIDE, int NR>
+__device__ __forceinline__ void bitonic_merge(double (&d)[NR], int (&j)[NR],
+                                              int lane) {
+  if constexpr (STRIDE >= 1) {
+    if constexpr (STRIDE == 64) {  // partner in the other register
+      const bool take = key_less(d[1], j[1], d[0], j[0]);  // SIZE == 128
+      const double t0 = d[0];
+      const int u0 = j[0];
+      d[0] = take ? d[1] : d[0];
+      j[0] = take ? j[1] : j[0];
+      d[1] = take ? t0 : d[1];
+      j[1] = take ? u0 : j[1];
+    } else {
+      bitonic_stage<SIZE, STRIDE, NR>(d, j, lane);
+    }
+    bitonic_merge<SIZE, STRIDE / 2, NR>(d, j, lane);
+  }
+}
+
+// Ascending sort of the 64 NR keys; padding keys are (inf, INT_MAX).
+template <int NR, int SIZE = 2>
+__device__ __forceinline__ void bitonic_sort(double (&d)[NR], int (&j)[NR],
+                                             int lane) {
+  if constexpr (SIZE <= 64 * NR) {
+    bitonic_merge<SIZE, SIZE / 2, NR>(d, j, lane);
+    bitonic_sort<NR, SIZE * 2>(d, j, lane);
+  }
+}
+
+// Stencil of one query from `base` compacted candidates: sort, write the
+// first n, return the n-th squared distance (wave-uniform).
+template <int NR>
+__device__ __forceinline__ double rank_sorted(const double* kd, const int* kj,
+                                              int base, int n, int lane,
+                                              int32_t* knn_row,
+                                              double* rho2_q) {
+  double d[NR];
+  int j[NR];
+#pragma unroll
+  for (int h = 0; h < NR; ++h) {
+    const int t = lane + 64 * h;
+    d[h] = t < base ? kd[t] : INFINITY;
+    j[h] = t < base ? kj[t] : 0x7FFFFFFF;
+  }
+  bitonic_sort<NR>(d, j, lane);
+  double nth = 0.0;
+#pragma unroll
+  for (int h = 0; h < NR; ++h) {
+    const int t = lane + 64 * h;
+    if (t < n) knn_row[t] = j[h];
+    if (t == n - 1) *rho2_q = d[h];
+    const int src = (n - 1) - 64 * h;
+    if (src >= 0 && src < 64) nth = readlane_f64_knn(d[h], src);
+  }
+  return nth;
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -192,10 +279,11 @@ __global__ __launch_bounds__(256) void cell_scatter_kernel(
 }
 
 // One wavefront per query.  Candidates with d^2 < T are compacted into LDS
-// in one pass and ranked exactly by (d^2, index); T starts from the previous
-// query's n-th distance (queries run in cell order, so neighbours have
-// nearly the same stencil radius) and is corrected by bisection when the
-// pass keeps fewer than n or more than kKeep candidates.  T never exceeds
+// in one pass and ordered exactly by (d^2, index) with an in-register
+// bitonic sort (64 or 128 keys); T starts from the previous query's n-th
+// distance (queries run in cell order, so neighbours have nearly the same
+// stencil radius) and is corrected by bisection when the pass keeps fewer
+// than n or more than 128 candidates.  T never exceeds
 // the squared distance to the boundary of the scanned block, so the result
 // is exact: every node outside the block is farther than every kept one.
 __global__ __launch_bounds__(256) void knn_query_kernel(
@@ -241,7 +329,11 @@ __global__ __launch_bounds__(256) void knn_query_kernel(
       const double cut = whole ? g.diag2 : b * b * (1.0 - 1e-9);
 
       double tlo = 0.0, thi = cut;  // bisection bracket for T
-      double T = (est > 0.0 && est * 1.3 < cut) ? est * 1.3 : cut;
+      int shrink = 0;
+      // first guess: 1.3 x the previous query's n-th squared distance, or
+      // the grid's expected one (the cell side is ~ the stencil radius)
+      const double guess = est > 0.0 ? est * 1.3 : g.s * g.s;
+      double T = guess < cut ? guess : cut;
       for (int it = 0; it < 64; ++it) {
         // one pass: compact every candidate with d^2 < T
         int base = 0;
@@ -277,13 +369,26 @@ __global__ __launch_bounds__(256) void knn_query_kernel(
           T = (thi < cut) ? 0.5 * (T + thi) : fmin(cut, T * 1.6);
           continue;
         }
-        if (base > kKeep) {
+        // more than the in-register sort holds: shrink T a few times, then
+        // (ties on a lattice) fall back to pairwise ranking of <= kKeep
+        if ((base > 128 && shrink < 8) || base > kKeep) {
+          ++shrink;
           thi = T;
           T = 0.5 * (tlo + T);
           continue;
         }
-        // exact rank by (d^2, index); ranks below n are the stencil
+        // exact order by (d^2, index); the first n are the stencil
         wave_sync();
+        if (base <= 128) {
+          est = (base <= 64)
+                    ? rank_sorted<1>(kd[w], kj[w], base, n, lane,
+                                     knn + (int64_t)qi * n, rho2 + qi)
+                    : rank_sorted<2>(kd[w], kj[w], base, n, lane,
+                                     knn + (int64_t)qi * n, rho2 + qi);
+          wave_sync();
+          done = true;
+          break;
+        }
         for (int t = lane; t < base; t += 64) {
           const double dt = kd[w][t];
           const int jt = kj[w][t];
