@@ -23,6 +23,10 @@ namespace {
 constexpr int kWaves = 4;    // wavefronts per block in the query kernel
 constexpr int kKeep = 256;   // LDS capacity for ranked candidates per wave
 constexpr int kRun = 16;     // consecutive (cell-ordered) queries per wave
+// first threshold: kGrow x the previous query's n-th squared distance; small
+// enough that about n (1 + 1.5 (kGrow - 1)) candidates pass, so most sets fit
+// one key per lane, large enough that few queries need a second pass
+constexpr double kGrow = 1.15;
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -330,9 +334,9 @@ __global__ __launch_bounds__(256) void knn_query_kernel(
 
       double tlo = 0.0, thi = cut;  // bisection bracket for T
       int shrink = 0;
-      // first guess: 1.3 x the previous query's n-th squared distance, or
+      // first guess: kGrow x the previous query's n-th squared distance, or
       // the grid's expected one (the cell side is ~ the stencil radius)
-      const double guess = est > 0.0 ? est * 1.3 : g.s * g.s;
+      const double guess = est > 0.0 ? est * kGrow : g.s * g.s;
       double T = guess < cut ? guess : cut;
       for (int it = 0; it < 64; ++it) {
         // one pass: compact every candidate with d^2 < T

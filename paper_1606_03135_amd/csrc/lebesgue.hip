@@ -228,7 +228,7 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
       if ((st = exclusive_scan_i32_to_i64(ctx, flag, N, pos))) return st;
       hipLaunchKernelGGL(lcompact_kernel, dim3(g1), dim3(256), 0, s, flag, pos,
                          N, list, npend);
-      const int64_t grid = hc[1] < ctx->num_cus * 64 ? hc[1] : ctx->num_cus * 64;
+      const int64_t grid = hc[1];  // one block per pending center
       if (!launch_weights_reg(ctx, P, grid))
         return fail(ctx, ORBF_EINVAL,
                     "Lebesgue covering needs the register weights kernel "

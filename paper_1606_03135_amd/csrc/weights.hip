@@ -351,7 +351,10 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
     if (st) return st;
   }
   const int64_t work = explicit_rows ? a->n_rows : a->N;
-  const int64_t grid = work < (int64_t)ctx->num_cus * 64 ? work : (int64_t)ctx->num_cus * 64;
+  // one block per possible stencil: blocks past the device-side count exit
+  // at once, and the hardware dispatcher balances the uneven stencil costs
+  // (a grid-stride loop would leave a tail of several stencils per slot)
+  const int64_t grid = work;
   if (grid <= 0) return ORBF_OK;
   static const bool force_lds = getenv("ORBF_WEIGHTS_LDS") != nullptr;
   // FP64 kernels by size: one wavefront (K <= 72), one workgroup of four

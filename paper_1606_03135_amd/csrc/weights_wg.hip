@@ -318,8 +318,7 @@ bool launch_wg(orbf_ctx* ctx, const WeightsParams& P, int64_t work) {
     attr_set = true;
   }
   if (dyn > 96 * 1024) return false;
-  const int64_t cap = (int64_t)ctx->num_cus * 4;
-  const int64_t grid = work < cap ? work : cap;
+  const int64_t grid = work;  // one workgroup per possible stencil
   hipLaunchKernelGGL((weights_wg_kernel<L, PL>), dim3((unsigned)grid),
                      dim3(kThreads), dyn, ctx->stream, P);
   return true;
