@@ -106,6 +106,9 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec);
  *   knn  : N*n   int32 output
  *   rho2 : N     FP64 output, squared stencil width rho_k^2 = squared
  *                distance to the n-th neighbour (Sec. 4.1)
+ * The context also keeps the n squared distances of every stencil (N*n
+ * FP64 of its scratch) together with the xyz and knn pointers; see
+ * orbf_select_overlapped_stencils.
  * Errors: EINVAL (d, n < 1, n > N, N > 2^31-1, NULL), EDUPLICATE at sync
  * time if two nodes coincide. */
 orbf_status orbf_build_nodes_knn(orbf_ctx* ctx, const double* xyz, int64_t N,
@@ -126,6 +129,12 @@ orbf_status orbf_build_nodes_knn(orbf_ctx* ctx, const double* xyz, int64_t N,
  *   owner     : N int32 output: center whose stencil computes row j, -1 for
  *               ineligible nodes (owner[k] == k for centers)
  *   p         : capacity N int32 output: p[c] = rows computed by centers[c]
+ * When xyz and knn are the arrays of this context's latest
+ * orbf_build_nodes_knn call (same pointers and sizes), the squared distances
+ * it recorded are used instead of gathering coordinates; they are the same
+ * values.  A caller that changes those arrays in place between the two
+ * calls must run orbf_build_nodes_knn again.  The same holds for the
+ * Lebesgue covering of orbf_compute_weights (mode c).
  * Errors: EINVAL (delta outside [0,1] or NaN, sizes, NULL). */
 orbf_status orbf_select_overlapped_stencils(
     orbf_ctx* ctx, const double* xyz, const int32_t* knn, const double* rho2,

@@ -64,6 +64,7 @@ void release_scratch(orbf_ctx* ctx) {
     b.bytes = 0;
   }
   ctx->held = 0;
+  ctx->d2_cache = D2Cache();
 }
 
 static int num_monomials(int d, int l) {
@@ -223,6 +224,7 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   t += want(64);                        // B_MISC2
   t += want(scan_tmp_elems((int64_t)Nn + 66) * 8);  // B_SCAN_TMP
   t += want(Nn * 4) + want(8);          // B_IR_FALLBACK, B_IR_COUNT
+  t += want(Nn * (size_t)n * 8);        // B_KNN_D2
   return t;
 }
 

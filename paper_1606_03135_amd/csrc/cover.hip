@@ -12,8 +12,9 @@
 //   3. a fixed number of parallel rounds (each undecided node is decided as
 //      soon as one predecessor is a center, or all predecessors are
 //      non-centers),
-//   4. a single-workgroup finish over the remaining undecided nodes in
-//      ascending order, so no host round trip is needed,
+//   4. rounds over the compacted list of nodes still undecided, then a
+//      single-workgroup finish over whatever remains, in ascending order,
+//      so no host round trip is needed,
 //   5. owners, the ascending center list and p per center.
 #include "orbf_internal.hpp"
 
@@ -22,18 +23,22 @@ namespace orbf {
 namespace {
 
 enum : int32_t { S_UNDECIDED = 0, S_CENTER = 1, S_COVERED = 2, S_INELIGIBLE = 3 };
-constexpr int kRounds = 10;
+constexpr int kRounds = 10;      // full rounds over all nodes
+constexpr int kListRounds = 24;  // rounds over the remaining undecided
 
+// Retention balls from the coordinates: one thread per node, gathering the
+// coordinates of its stencil.
 __global__ __launch_bounds__(256) void ball_kernel(
     const double* __restrict__ x, const int32_t* __restrict__ knn,
     const double* __restrict__ rho2, int64_t N, int d, int n, double t2,
     const uint8_t* __restrict__ eligible, uint64_t* __restrict__ ball,
-    int32_t* __restrict__ indeg, int32_t* __restrict__ state) {
+    int32_t* __restrict__ indeg, int32_t* __restrict__ state, int32_t s_open,
+    int32_t s_inel) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= N) return;
   uint64_t b0 = 0, b1 = 0;
   const bool ec = eligible == nullptr || eligible[c] != 0;
-  state[c] = ec ? S_UNDECIDED : S_INELIGIBLE;
+  state[c] = ec ? s_open : s_inel;
   if (ec) {
     const double thr = t2 * rho2[c];
     const double cx = x[c * d], cy = x[c * d + 1];
@@ -57,6 +62,44 @@ __global__ __launch_bounds__(256) void ball_kernel(
   }
   ball[2 * c] = b0;
   ball[2 * c + 1] = b1;
+}
+
+// Retention balls from the squared distances the kNN recorded for the same
+// arrays (identical values: same formula, same operand order): one
+// wavefront per node, taken in the kNN's cell order so the distance rows
+// stream; lane q tests stencil position q and a ballot forms the mask.
+__global__ __launch_bounds__(256) void ball_d2_kernel(
+    const double* __restrict__ d2s, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ knn, const double* __restrict__ rho2,
+    int64_t N, int n, double t2, const uint8_t* __restrict__ eligible,
+    uint64_t* __restrict__ ball, int32_t* __restrict__ indeg,
+    int32_t* __restrict__ state, int32_t s_open, int32_t s_inel) {
+  const int64_t qs = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (qs >= N) return;  // whole wavefront
+  const int64_t c = perm[qs];
+  const double* d2 = d2s + qs * n;
+  const bool ec = eligible == nullptr || eligible[c] != 0;
+  const double thr = t2 * rho2[c];
+  uint64_t b[2] = {0ull, 0ull};
+  for (int h = 0; h < 2 && 64 * h < n; ++h) {
+    const int q = lane + 64 * h;
+    bool in = false;
+    if (ec && q >= 1 && q < n) {
+      const int32_t j = knn[c * n + q];
+      if (j > c && j < N && (eligible == nullptr || eligible[j] != 0) &&
+          d2[q] <= thr) {
+        in = true;
+        atomicAdd(&indeg[j], 1);
+      }
+    }
+    b[h] = __ballot(in);
+  }
+  if (lane == 0) {
+    state[c] = ec ? s_open : s_inel;
+    ball[2 * c] = b[0];
+    ball[2 * c + 1] = b[1];
+  }
 }
 
 __global__ __launch_bounds__(256) void pred_fill_kernel(
@@ -100,6 +143,22 @@ __global__ __launch_bounds__(256) void round_kernel(
   if (state[j] != S_UNDECIDED) return;
   const int32_t s = decide(pred, start[j], start[j + 1], state);
   if (s != S_UNDECIDED) __atomic_store_n(&state[j], s, __ATOMIC_RELAXED);
+}
+
+// A round over the compacted list of nodes still undecided after the full
+// rounds (grid-stride; the list length is on the device).
+__global__ __launch_bounds__(256) void round_list_kernel(
+    const int32_t* __restrict__ pred, const int64_t* __restrict__ start,
+    const int32_t* __restrict__ list, const int64_t* __restrict__ count,
+    int32_t* state) {
+  const int64_t cnt = *count;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < cnt;
+       t += (int64_t)gridDim.x * 256) {
+    const int32_t j = list[t];
+    if (__atomic_load_n(&state[j], __ATOMIC_RELAXED) != S_UNDECIDED) continue;
+    const int32_t s = decide(pred, start[j], start[j + 1], state);
+    if (s != S_UNDECIDED) __atomic_store_n(&state[j], s, __ATOMIC_RELAXED);
+  }
 }
 
 __global__ __launch_bounds__(256) void undecided_flag_kernel(
@@ -195,6 +254,23 @@ __global__ __launch_bounds__(256) void zero_i32_kernel(int32_t* p, int64_t n) {
 
 }  // namespace
 
+void launch_ball(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
+                 const double* rho2, int64_t N, int d, int n, double t2,
+                 const uint8_t* eligible, uint64_t* ball, int32_t* indeg,
+                 int32_t* state, int32_t s_open, int32_t s_inel) {
+  hipStream_t s = ctx->stream;
+  if (ctx->d2_cache.matches(xyz, knn, N, d, n)) {
+    hipLaunchKernelGGL(ball_d2_kernel, dim3((unsigned)((N + 3) / 4)),
+                       dim3(256), 0, s, ctx->d2_cache.d2, ctx->d2_cache.perm,
+                       knn, rho2, N, n, t2, eligible, ball, indeg, state,
+                       s_open, s_inel);
+  } else {
+    hipLaunchKernelGGL(ball_kernel, dim3((unsigned)((N + 255) / 256)),
+                       dim3(256), 0, s, xyz, knn, rho2, N, d, n, t2, eligible,
+                       ball, indeg, state, s_open, s_inel);
+  }
+}
+
 orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
                          const double* rho2, int64_t N, int d, int n,
                          double t2, const uint8_t* eligible, int32_t* centers,
@@ -213,8 +289,8 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   const unsigned gz = (unsigned)((N + 256) / 256 < 65535 ? (N + 256) / 256 : 65535);
   hipLaunchKernelGGL(zero_i32_kernel, dim3(gz), dim3(256), 0, s, indeg, N + 1);
   hipLaunchKernelGGL(zero_i32_kernel, dim3(gz), dim3(256), 0, s, fill, N + 1);
-  hipLaunchKernelGGL(ball_kernel, dim3(g), dim3(256), 0, s, xyz, knn, rho2, N,
-                     d, n, t2, eligible, ball, indeg, state);
+  launch_ball(ctx, xyz, knn, rho2, N, d, n, t2, eligible, ball, indeg, state,
+              S_UNDECIDED, S_INELIGIBLE);
   st = exclusive_scan_i32_to_i64(ctx, indeg, N, pstart);
   if (st) return st;
   // the predecessor array is sized from the edge count, known only on the
@@ -236,6 +312,10 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   if (st) return st;
   hipLaunchKernelGGL(compact_kernel, dim3(g), dim3(256), 0, s, flag, pos, N,
                      list);
+  // rounds over the stragglers only, then one workgroup for what is left
+  for (int r = 0; r < kListRounds; ++r)
+    hipLaunchKernelGGL(round_list_kernel, dim3(256), dim3(256), 0, s, pred,
+                       pstart, list, pos + N, state);
   hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, s, pred, pstart,
                      list, pos + N, state);
   hipLaunchKernelGGL(owner_kernel, dim3(g), dim3(256), 0, s, pred, pstart,

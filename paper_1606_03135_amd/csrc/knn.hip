@@ -94,11 +94,13 @@ __device__ __forceinline__ void bitonic_sort(double (&d)[NR], int (&j)[NR],
 }
 
 // Stencil of one query from `base` compacted candidates: sort, write the
-// first n, return the n-th squared distance (wave-uniform).
+// first n indices and squared distances, return the n-th squared distance
+// (wave-uniform).
 template <int NR>
 __device__ __forceinline__ double rank_sorted(const double* kd, const int* kj,
                                               int base, int n, int lane,
                                               int32_t* knn_row,
+                                              double* d2_row,
                                               double* rho2_q) {
   double d[NR];
   int j[NR];
@@ -113,7 +115,10 @@ __device__ __forceinline__ double rank_sorted(const double* kd, const int* kj,
 #pragma unroll
   for (int h = 0; h < NR; ++h) {
     const int t = lane + 64 * h;
-    if (t < n) knn_row[t] = j[h];
+    if (t < n) {
+      knn_row[t] = j[h];
+      d2_row[t] = d[h];
+    }
     if (t == n - 1) *rho2_q = d[h];
     const int src = (n - 1) - 64 * h;
     if (src >= 0 && src < 64) nth = readlane_f64_knn(d[h], src);
@@ -290,11 +295,13 @@ __global__ __launch_bounds__(256) void cell_scatter_kernel(
 // than n or more than 128 candidates.  T never exceeds
 // the squared distance to the boundary of the scanned block, so the result
 // is exact: every node outside the block is farther than every kept one.
-__global__ __launch_bounds__(256) void knn_query_kernel(
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
     const double* __restrict__ xs, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ cstart, const GridParams* __restrict__ gpp,
     int64_t N, int d, int n, int32_t* __restrict__ knn,
-    double* __restrict__ rho2, DevStatus* __restrict__ st) {
+    double* __restrict__ rho2, double* __restrict__ d2,
+    DevStatus* __restrict__ st) {
   __shared__ double kd[kWaves][kKeep];
   __shared__ int kj[kWaves][kKeep];
   __shared__ double kth[kWaves];
@@ -386,9 +393,11 @@ __global__ __launch_bounds__(256) void knn_query_kernel(
         if (base <= 128) {
           est = (base <= 64)
                     ? rank_sorted<1>(kd[w], kj[w], base, n, lane,
-                                     knn + (int64_t)qi * n, rho2 + qi)
+                                     knn + (int64_t)qi * n,
+                                     d2 + qs * n, rho2 + qi)
                     : rank_sorted<2>(kd[w], kj[w], base, n, lane,
-                                     knn + (int64_t)qi * n, rho2 + qi);
+                                     knn + (int64_t)qi * n,
+                                     d2 + qs * n, rho2 + qi);
           wave_sync();
           done = true;
           break;
@@ -404,6 +413,7 @@ __global__ __launch_bounds__(256) void knn_query_kernel(
           }
           if (r < n) {
             knn[(int64_t)qi * n + r] = jt;
+            d2[qs * n + r] = dt;
             if (r == n - 1) {
               rho2[qi] = dt;
               kth[w] = dt;  // n-th distance, the next query's first guess
@@ -443,6 +453,9 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   auto* cstart = (int64_t*)scratch(ctx, B_CELL_START, (size_t)(cap + 2) * 8, &st);
   auto* perm = (int32_t*)scratch(ctx, B_PERM, (size_t)N * 4, &st);
   auto* xs = (double*)scratch(ctx, B_XS, (size_t)N * d * 8, &st);
+  // squared distance of every stencil member, kept for the covering, in
+  // cell order (row qs belongs to node perm[qs]): contiguous writes
+  auto* d2 = (double*)scratch(ctx, B_KNN_D2, (size_t)N * n * 8, &st);
   if (st) return st;
   double alpha = 0.9;
   if (const char* e = getenv("ORBF_KNN_ALPHA")) alpha = atof(e);
@@ -463,7 +476,8 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   const int64_t qblocks = (N + kWaves * kRun - 1) / (kWaves * kRun);
   hipLaunchKernelGGL(knn_query_kernel, dim3((unsigned)qblocks),
                      dim3(64 * kWaves), 0, s, xs, perm, cstart, gp, N, d, n,
-                     knn, rho2, ctx->status);
+                     knn, rho2, d2, ctx->status);
+  ctx->d2_cache = {xyz, knn, N, d, n, d2, perm};
   return hip_check(ctx, hipGetLastError(), "knn");
 }
 

@@ -29,38 +29,6 @@ enum : int32_t {
   L_INELIGIBLE = 4
 };
 
-__global__ __launch_bounds__(256) void lball_kernel(
-    const double* __restrict__ x, const int32_t* __restrict__ knn,
-    const double* __restrict__ rho2, int64_t N, int d, int n, double t2,
-    const uint8_t* __restrict__ eligible, uint64_t* __restrict__ ball,
-    int32_t* __restrict__ indeg, int32_t* __restrict__ state) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= N) return;
-  uint64_t b0 = 0, b1 = 0;
-  const bool ec = eligible == nullptr || eligible[c] != 0;
-  state[c] = ec ? L_UNDECIDED : L_INELIGIBLE;
-  if (ec) {
-    const double thr = t2 * rho2[c];
-    const double cx = x[c * d], cy = x[c * d + 1];
-    const double cz = (d == 3) ? x[c * d + 2] : 0.0;
-    const int32_t* st = knn + c * n;
-    for (int q = 1; q < n; ++q) {
-      const int32_t j = st[q];
-      if (j <= c || j >= N) continue;
-      if (eligible != nullptr && eligible[j] == 0) continue;
-      const double* p = x + (int64_t)j * d;
-      const double d2 =
-          exact_sqdist(cx, cy, cz, p[0], p[1], d == 3 ? p[2] : 0.0, d);
-      if (d2 <= thr) {
-        if (q < 64) b0 |= 1ull << q; else b1 |= 1ull << (q - 64);
-        atomicAdd(&indeg[j], 1);
-      }
-    }
-  }
-  ball[2 * c] = b0;
-  ball[2 * c + 1] = b1;
-}
-
 // predecessor entries carry the stencil position: c | (q << 25)
 __global__ __launch_bounds__(256) void lpred_kernel(
     const int32_t* __restrict__ knn, int64_t N, int n,
@@ -199,8 +167,8 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
   hipLaunchKernelGGL(lzero_kernel, dim3(gz), dim3(256), 0, s, fill, N + 1);
   hipLaunchKernelGGL(lzero_kernel, dim3(gz), dim3(256), 0, s, (int32_t*)acc,
                      4 * N);
-  hipLaunchKernelGGL(lball_kernel, dim3(g), dim3(256), 0, s, P0.xyz, P0.knn,
-                     P0.rho2, N, d, n, t2, eligible, ball, indeg, state);
+  launch_ball(ctx, P0.xyz, P0.knn, P0.rho2, N, d, n, t2, eligible, ball,
+              indeg, state, L_UNDECIDED, L_INELIGIBLE);
   if ((st = exclusive_scan_i32_to_i64(ctx, indeg, N, pstart))) return st;
   hipLaunchKernelGGL(lpred_kernel, dim3(g), dim3(256), 0, s, P0.knn, N, n,
                      ball, pstart, fill, pred);

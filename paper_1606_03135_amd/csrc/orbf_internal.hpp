@@ -56,6 +56,23 @@ struct Buffer {
   size_t bytes = 0;
 };
 
+// The squared distances of the stencils of the context's last kNN call
+// (B_KNN_D2, one row of n per node in cell order: row s belongs to node
+// perm[s]) and the arrays they belong to.  The covering reuses them when it
+// is handed the same xyz and knn arrays.
+struct D2Cache {
+  const double* xyz = nullptr;
+  const int32_t* knn = nullptr;
+  int64_t N = 0;
+  int d = 0, n = 0;
+  const double* d2 = nullptr;
+  const int32_t* perm = nullptr;  // B_PERM of the same call
+  bool matches(const double* x, const int32_t* k, int64_t N_, int d_,
+               int n_) const {
+    return d2 && x == xyz && k == knn && N_ == N && d_ == d && n_ == n;
+  }
+};
+
 }  // namespace orbf
 
 struct orbf_ctx {
@@ -85,6 +102,7 @@ struct orbf_ctx {
   float phase_ms[5] = {0, 0, 0, 0, 0};
   bool phase_valid[5] = {false, false, false, false, false};
   int32_t* host_counter = nullptr;  // pinned, covering round control
+  orbf::D2Cache d2_cache;
 };
 
 namespace orbf {
@@ -113,6 +131,7 @@ enum BufId {
   B_MISC2,
   B_IR_FALLBACK,
   B_IR_COUNT,
+  B_KNN_D2,
 };
 
 // ctx helpers (api.hip)
@@ -139,6 +158,13 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
 orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        const int32_t* owner, const double* W,
                        int64_t* row_ptr, int32_t* col, double* val);
+
+// retention-ball masks, in-degrees and initial states (cover.hip); uses the
+// kNN's recorded squared distances when they belong to xyz and knn
+void launch_ball(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
+                 const double* rho2, int64_t N, int d, int n, double t2,
+                 const uint8_t* eligible, uint64_t* ball, int32_t* indeg,
+                 int32_t* state, int32_t s_open, int32_t s_inel);
 
 // batched builds and serving (batch.hip)
 orbf_status build_set(orbf_ctx* c, const orbf_set_desc& s);

@@ -327,3 +327,20 @@ def test_workspace_size_bounds_scratch(orbf, case):
             orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"],
                           ctx=orbf.Context(0, budget=ws // 2), **kw)
         assert e.value.code == orbf.EBUDGET
+
+
+def test_cover_recorded_distances_match_gathered(orbf, ctx):
+    """The covering from the kNN's recorded squared distances equals the one
+    from gathered coordinates (a copy of knn is not the recorded array)."""
+    for N, n, delta in ((20000, 50, 0.3), (3000, 105, 0.5)):
+        x = nodesets.ball(N, 2)["x"]
+        xd = gpu(x)
+        k, r = orbf.build_nodes_knn(ctx, xd, n)
+        ca, na, oa, pa = orbf.select_overlapped_stencils(ctx, xd, k, r, delta)
+        cb, nb, ob, pb = orbf.select_overlapped_stencils(ctx, xd, k.clone(),
+                                                         r, delta)
+        ctx.sync()
+        nc = int(na.item())
+        assert nc == int(nb.item())
+        assert torch.equal(oa, ob)
+        assert torch.equal(ca[:nc], cb[:nc]) and torch.equal(pa[:nc], pb[:nc])
