@@ -270,36 +270,34 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
               __ballot(key0 == kmax) & (0xFFull << (8 * cc));
           const int rp = (__ffsll((long long)who) - 1) & 7;
           const int piv = 8 * iip + rp;
-          // 2. retire the pivot row; write it, and the column of unscaled
-          //    multipliers, to LDS
-          sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
-            constexpr int ii = decltype(iic)::value;
-            act[ii] = (ii == iip && r == rp) ? 0u : act[ii];
-          });
-          // the pivot value itself comes by readlane, so its reciprocal is
-          // under way while the LDS broadcast is in flight
+          // 2. the column of unscaled multipliers, then (one uniform case
+          //    per row block) retire the pivot row, write it to LDS and
+          //    overwrite its own multiplier with zero, so the update below
+          //    needs no per-row test; the pivot value itself comes by
+          //    readlane, so its reciprocal is under way while the LDS
+          //    broadcast is in flight
+          if (c == cc) {
+            sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
+              constexpr int ii = decltype(iic)::value;
+              lbuf[r * L + ii] = a[ii][kb];
+            });
+          }
           double upiv = 0.0;
           sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
             constexpr int ii = decltype(iic)::value;
             if (iip == ii) {
               __asm__ volatile("; pivot row out %0" ::"i"(ii));
               upiv = readlane_f64(a[ii][kb], 8 * cc + rp);
+              act[ii] = (r == rp) ? 0u : act[ii];
               if (r == rp) {
                 sfor<kb, LC>([&](auto jjc) __attribute__((always_inline)) {
                   constexpr int jj = decltype(jjc)::value;
                   ubuf[c * LC + jj] = a[ii][jj];
                 });
+                if (c == cc) lbuf[r * L + ii] = 0.0;
               }
             }
           });
-          // multipliers of column k; the pivot row's is written as zero, so
-          // the update below needs no per-row test
-          if (c == cc) {
-            sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
-              constexpr int ii = decltype(iic)::value;
-              lbuf[r * L + ii] = (ii == iip && r == rp) ? 0.0 : a[ii][kb];
-            });
-          }
           if (lane == 0) srank[piv] = k;
           if (!(upiv != 0.0)) singular = true;
           const double dk = singular ? 0.0 : recip(upiv);
