@@ -136,6 +136,8 @@ orbf_status orbf_create(int device, void* hip_stream, size_t hbm_budget_bytes,
     ctx->num_cus = prop.multiProcessorCount;
   if (hipMalloc(&ctx->status, sizeof(DevStatus)) != hipSuccess ||
       hipHostMalloc((void**)&ctx->status_host, sizeof(DevStatus),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->host_counter, sizeof(int64_t),
                     hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return ORBF_ENOMEM;
@@ -159,6 +161,7 @@ void orbf_destroy(orbf_ctx* ctx) {
     if (b.ptr) hipFree(b.ptr);
   if (ctx->status) hipFree(ctx->status);
   if (ctx->status_host) hipHostFree(ctx->status_host);
+  if (ctx->host_counter) hipHostFree(ctx->host_counter);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);
   if (ctx->owns_stream && ctx->stream) hipStreamDestroy(ctx->stream);
@@ -221,7 +224,7 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   t += want(Nn * 4);                    // B_STATE
   t += want(edges * 4);                 // B_PRED
   t += want(Nn * 16);                   // B_W_TMP (Lebesgue covering)
-  t += want(64);                        // B_MISC2
+  t += want(64) + want(8);              // B_MISC2, B_MISC
   t += want(scan_tmp_elems((int64_t)Nn + 66) * 8);  // B_SCAN_TMP
   t += want(Nn * 4) + want(8);          // B_IR_FALLBACK, B_IR_COUNT
   t += want(Nn * (size_t)n * 8);        // B_KNN_D2

@@ -16,6 +16,8 @@
 //      single-workgroup finish over whatever remains, in ascending order,
 //      so no host round trip is needed,
 //   5. owners, the ascending center list and p per center.
+#include <utility>
+
 #include "orbf_internal.hpp"
 
 namespace orbf {
@@ -25,6 +27,9 @@ namespace {
 enum : int32_t { S_UNDECIDED = 0, S_CENTER = 1, S_COVERED = 2, S_INELIGIBLE = 3 };
 constexpr int kRounds = 10;      // full rounds over all nodes
 constexpr int kListRounds = 24;  // rounds over the remaining undecided
+constexpr int kCheck = 64;       // further rounds between open-count checks
+constexpr int kMaxCheck = 256;   // checks before the finish takes the rest
+constexpr int64_t kFinishLeft = 256;  // open nodes left to the finish
 
 // Retention balls from the coordinates: one thread per node, gathering the
 // coordinates of its stencil.
@@ -160,6 +165,26 @@ __global__ __launch_bounds__(256) void round_list_kernel(
     if (s != S_UNDECIDED) __atomic_store_n(&state[j], s, __ATOMIC_RELAXED);
   }
 }
+
+// Number of list entries still undecided (one atomic per block).
+__global__ __launch_bounds__(256) void count_open_kernel(
+    const int32_t* __restrict__ list, const int64_t* __restrict__ count,
+    const int32_t* state, int64_t* __restrict__ open) {
+  __shared__ int blk;
+  if (threadIdx.x == 0) blk = 0;
+  __syncthreads();
+  const int64_t cnt = *count;
+  int mine = 0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < cnt;
+       t += (int64_t)gridDim.x * 256)
+    mine += __atomic_load_n(&state[list[t]], __ATOMIC_RELAXED) == S_UNDECIDED;
+  if (mine) atomicAdd(&blk, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && blk)
+    atomicAdd((unsigned long long*)open, (unsigned long long)blk);
+}
+
+__global__ void zero_i64_kernel(int64_t* p) { *p = 0; }
 
 __global__ __launch_bounds__(256) void undecided_flag_kernel(
     const int32_t* __restrict__ state, int64_t N, int32_t* __restrict__ flag) {
@@ -312,10 +337,57 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   if (st) return st;
   hipLaunchKernelGGL(compact_kernel, dim3(g), dim3(256), 0, s, flag, pos, N,
                      list);
-  // rounds over the stragglers only, then one workgroup for what is left
-  for (int r = 0; r < kListRounds; ++r)
-    hipLaunchKernelGGL(round_list_kernel, dim3(256), dim3(256), 0, s, pred,
-                       pstart, list, pos + N, state);
+  // Rounds over the stragglers only.  An input order with long dependency
+  // chains (a raster-ordered grid) needs as many rounds as the chains are
+  // long: an eager call keeps launching rounds, checking the open count
+  // every kCheck rounds, and records how many it used; a call under graph
+  // capture cannot check and replays the recorded count.  One workgroup
+  // finishes whatever is left either way.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipStreamIsCapturing(s, &cap);
+  const std::pair<const void*, int64_t> key(knn, N);
+  int recorded = -1;
+  for (size_t i = 0; i < ctx->cover_keys.size(); ++i)
+    if (ctx->cover_keys[i] == key) recorded = ctx->cover_rounds[i];
+  auto rounds = [&](int k) {
+    for (int r = 0; r < k; ++r)
+      hipLaunchKernelGGL(round_list_kernel, dim3(256), dim3(256), 0, s, pred,
+                         pstart, list, pos + N, state);
+  };
+  int used = kListRounds;
+  if (cap != hipStreamCaptureStatusNone) {
+    rounds(recorded > 0 ? recorded : kListRounds);
+  } else {
+    rounds(kListRounds);
+    auto* open = (int64_t*)scratch(ctx, B_MISC, 8, &st);
+    if (st) return st;
+    for (int batch = 0; batch < kMaxCheck; ++batch) {
+      hipLaunchKernelGGL(zero_i64_kernel, dim3(1), dim3(1), 0, s, open);
+      hipLaunchKernelGGL(count_open_kernel, dim3(256), dim3(256), 0, s, list,
+                         pos + N, state, open);
+      hipError_t e = hipMemcpyAsync(ctx->host_counter, open, sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if ((st = hip_check(ctx, e, "cover: open count"))) return st;
+      if (*ctx->host_counter <= kFinishLeft) break;
+      rounds(kCheck);
+      used += kCheck;
+    }
+    bool found = false;
+    for (size_t i = 0; i < ctx->cover_keys.size(); ++i)
+      if (ctx->cover_keys[i] == key) {
+        ctx->cover_rounds[i] = used;
+        found = true;
+      }
+    if (!found) {
+      if (ctx->cover_keys.size() >= 4096) {
+        ctx->cover_keys.clear();
+        ctx->cover_rounds.clear();
+      }
+      ctx->cover_keys.push_back(key);
+      ctx->cover_rounds.push_back(used);
+    }
+  }
   hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(1024), 0, s, pred, pstart,
                      list, pos + N, state);
   hipLaunchKernelGGL(owner_kernel, dim3(g), dim3(256), 0, s, pred, pstart,

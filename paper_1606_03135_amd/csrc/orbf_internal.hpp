@@ -101,7 +101,11 @@ struct orbf_ctx {
   int graph_seen = 0;
   float phase_ms[5] = {0, 0, 0, 0, 0};
   bool phase_valid[5] = {false, false, false, false, false};
-  int32_t* host_counter = nullptr;  // pinned, covering round control
+  int64_t* host_counter = nullptr;  // pinned, covering round control
+  // rounds over the covering's straggler list that each (xyz, knn, N)
+  // needed in an eager call; a captured call replays that many
+  std::vector<std::pair<const void*, int64_t>> cover_keys;
+  std::vector<int> cover_rounds;
   orbf::D2Cache d2_cache;
 };
 
