@@ -221,6 +221,18 @@ def bench_batched(args, torch, orbf, nodesets):
     gen_s = time.perf_counter() - t0
     _log(f"{len(specs)} node sets generated in {gen_s:.1f} s")
     ctx = orbf.Context(0)
+    tuned = None
+    if not args.no_tune:
+        from paper_1606_03135_amd import tune
+        rep, tune_s = tune.tune_sets(
+            ctx, [dict(xyz=x, n=s["n"], m=s["m"], l=s["l"], delta=s["delta"])
+                  for s, x in zip(specs, xs)], reps=2)
+        picks = {}
+        for r in rep:
+            picks[r["pick"]] = picks.get(r["pick"], 0) + 1
+        tuned = {"classes": len(rep), "picks": picks, "tune_s": tune_s}
+        _log(f"tuned {len(rep)} (K, p-class) classes in {tune_s:.1f} s: "
+             f"{picks}")
 
     def sets_for(prec):
         return [dict(xyz=x, n=s["n"], m=s["m"], l=s["l"], delta=s["delta"],
@@ -277,6 +289,7 @@ def bench_batched(args, torch, orbf, nodesets):
         "corrections_mean": float(st[ok].mean()) if ok.any() else None,
         "fp64_rows": float((~ok).mean()),
         "node_generation_s": gen_s,
+        "autotuned": tuned,
     }
 
 
@@ -367,6 +380,8 @@ def main():
                          "whole workload)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched: skip the schedule autotuner")
     ap.add_argument("--sets", type=int, default=512)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=128)

@@ -210,6 +210,34 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
                               const double* W, int64_t* row_ptr, int32_t* col,
                               double* val);
 
+/* Kernel schedules for the weights.  Stencils of one system size K = n + M
+ * are solved by one of these kernels; which is fastest depends on K and on
+ * how many rows a stencil keeps, estimated as n (1-delta)^d: p-class 0 for
+ * at most 8, p-class 1 above (explicit rows are p-class 0).  The table is
+ * filled by an autotuner that times the candidates (Python:
+ * paper_1606_03135_amd.tune) and consulted by orbf_compute_weights; sizes
+ * without an entry use WAVE16 for K <= 72 and GROUP16 up to 144.  Batched
+ * builds pass the table to their workers. */
+typedef enum orbf_schedule {
+  ORBF_SCHED_DEFAULT = -1,
+  ORBF_SCHED_WAVE16 = 0,  /* one wavefront per stencil, 16 right-hand sides
+                             per pass (K <= 72)                              */
+  ORBF_SCHED_WAVE8 = 1,   /* one wavefront, 8 right-hand sides per pass
+                             (K <= 72): fewer registers                      */
+  ORBF_SCHED_GROUP16 = 2  /* four wavefronts on a 16 x 16 lane grid, 16
+                             right-hand sides per pass (K <= 144)            */
+} orbf_schedule;
+
+/* Set (or with ORBF_SCHED_DEFAULT clear) the schedule of (K, pclass).
+ * EINVAL if the schedule cannot serve K. */
+orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,
+                              orbf_schedule schedule);
+
+/* Copy the table out: up to cap rows of (K, pclass, schedule) to out (host,
+ * 3*cap int32); *count receives the number of rows. */
+orbf_status orbf_get_schedules(orbf_ctx* ctx, int32_t* out, int cap,
+                               int* count);
+
 /* Phase timing of the most recent calls on this context, in milliseconds of
  * stream time (HIP events around each entry point's kernels): [0] kNN,
  * [1] covering, [2] weights, [3] CSR, [4] duration of the weights kernel's

@@ -67,6 +67,13 @@ void release_scratch(orbf_ctx* ctx) {
   ctx->d2_cache = D2Cache();
 }
 
+int schedule_for(const orbf_ctx* ctx, int K, int pclass) {
+  for (size_t i = 0; i + 2 < ctx->schedules.size(); i += 3)
+    if (ctx->schedules[i] == K && ctx->schedules[i + 1] == pclass)
+      return ctx->schedules[i + 2];
+  return ORBF_SCHED_DEFAULT;
+}
+
 static int num_monomials(int d, int l) {
   long num = 1, den = 1;
   for (int i = 1; i <= d; ++i) {
@@ -310,6 +317,39 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
   hipSetDevice(ctx->device);
   PhaseTimer tm(ctx, 3);
   return launch_csr(ctx, N, n, knn, owner, W, row_ptr, col, val);
+}
+
+orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,
+                              orbf_schedule schedule) {
+  if (!ctx) return ORBF_EINVAL;
+  if (K < 1 || K > 160 || pclass < 0 || pclass > 1)
+    return fail(ctx, ORBF_EINVAL, "schedule: K in 1..160, pclass 0 or 1");
+  if ((schedule == ORBF_SCHED_WAVE16 || schedule == ORBF_SCHED_WAVE8) &&
+      K > 72)
+    return fail(ctx, ORBF_EINVAL, "one-wavefront schedules need K <= 72");
+  if (schedule == ORBF_SCHED_GROUP16 && K > 144)
+    return fail(ctx, ORBF_EINVAL, "the workgroup schedule needs K <= 144");
+  if (schedule < ORBF_SCHED_DEFAULT || schedule > ORBF_SCHED_GROUP16)
+    return fail(ctx, ORBF_EINVAL, "unknown schedule");
+  auto& t = ctx->schedules;
+  for (size_t i = 0; i + 2 < t.size(); i += 3)
+    if (t[i] == K && t[i + 1] == pclass) {
+      t.erase(t.begin() + i, t.begin() + i + 3);
+      break;
+    }
+  if (schedule != ORBF_SCHED_DEFAULT) t.insert(t.end(), {K, pclass, schedule});
+  drop_graph(ctx);
+  return ORBF_OK;
+}
+
+orbf_status orbf_get_schedules(orbf_ctx* ctx, int32_t* out, int cap,
+                               int* count) {
+  if (!ctx || !count || (cap > 0 && !out)) return ORBF_EINVAL;
+  const int rows = (int)(ctx->schedules.size() / 3);
+  for (int i = 0; i < rows && i < cap; ++i)
+    for (int k = 0; k < 3; ++k) out[3 * i + k] = ctx->schedules[3 * i + k];
+  *count = rows;
+  return ORBF_OK;
 }
 
 orbf_status orbf_phase_times(orbf_ctx* ctx, double* ms5) {

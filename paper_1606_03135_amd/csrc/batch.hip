@@ -189,6 +189,7 @@ static orbf_status enqueue_batch(orbf_ctx* ctx, const orbf_set_desc* sets,
     plan[w].push_back(i);
     load[w] += cost[i];
   }
+  for (int w = 0; w < nw; ++w) ctx->workers[w]->schedules = ctx->schedules;
   hipError_t e = hipEventRecord(ctx->fork_ev, origin);
   if (e != hipSuccess) return hip_check(ctx, e, "batch fork");
   for (int w = 0; w < nw; ++w) {

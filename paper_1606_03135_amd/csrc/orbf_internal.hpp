@@ -106,6 +106,8 @@ struct orbf_ctx {
   // needed in an eager call; a captured call replays that many
   std::vector<std::pair<const void*, int64_t>> cover_keys;
   std::vector<int> cover_rounds;
+  // weights kernel schedules: rows of (K, pclass, orbf_schedule)
+  std::vector<int> schedules;
   orbf::D2Cache d2_cache;
 };
 
@@ -169,6 +171,9 @@ void launch_ball(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
                  const double* rho2, int64_t N, int d, int n, double t2,
                  const uint8_t* eligible, uint64_t* ball, int32_t* indeg,
                  int32_t* state, int32_t s_open, int32_t s_inel);
+
+// schedule of (K, pclass), ORBF_SCHED_DEFAULT if none (api.hip)
+int schedule_for(const orbf_ctx* ctx, int K, int pclass);
 
 // batched builds and serving (batch.hip)
 orbf_status build_set(orbf_ctx* c, const orbf_set_desc& s);

@@ -357,10 +357,16 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   const int64_t grid = work;
   if (grid <= 0) return ORBF_OK;
   static const bool force_lds = getenv("ORBF_WEIGHTS_LDS") != nullptr;
-  // FP64 kernels by size: one wavefront (K <= 72), one workgroup of four
-  // (K <= 144), else the LDS-resident kernel
+  // FP64 kernels: the tuned schedule of (K, p-class) if there is one, else
+  // one wavefront (K <= 72), one workgroup of four (K <= 144), else the
+  // LDS-resident kernel.  p-class: expected kept rows n (1-delta)^d > 8.
+  const double keep = explicit_rows ? 1.0 : n * pow(t2, 0.5 * d);
+  const int sched = schedule_for(ctx, K, keep > 8.0 ? 1 : 0);
   auto fp64 = [&](const WeightsParams& Q) {
-    if (launch_weights_reg(ctx, Q, grid)) return;
+    if (sched == ORBF_SCHED_GROUP16 && launch_weights_wg(ctx, Q, work)) return;
+    if (sched != ORBF_SCHED_GROUP16 &&
+        launch_weights_reg(ctx, Q, grid, sched == ORBF_SCHED_WAVE8 ? 1 : 2))
+      return;
     if (launch_weights_wg(ctx, Q, work)) return;
     hipLaunchKernelGGL(weights_lds_kernel, dim3((unsigned)grid), dim3(64),
                        lds_bytes(pcap), ctx->stream, Q);

@@ -192,7 +192,8 @@ __device__ __forceinline__ double recip(double x) {
   return y;
 }
 
-bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid);
+bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid,
+                        int pl = 2);
 bool launch_weights_ir(orbf_ctx* ctx, const WeightsParams& P, int64_t grid);
 bool launch_weights_wg(orbf_ctx* ctx, const WeightsParams& P, int64_t work);
 void launch_ir_prepare(orbf_ctx* ctx, int32_t* ir_steps, int64_t N,

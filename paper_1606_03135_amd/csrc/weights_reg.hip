@@ -389,28 +389,35 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
 
 }  // namespace
 
-// Launch the register kernel if a variant covers K; returns false otherwise.
-bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid) {
+// Launch the register kernel if a variant covers K; `pl` = 1 or 2 blocks of
+// eight right-hand sides per pass.  Returns false if no variant covers K.
+bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid,
+                        int pl) {
   if (P.M > 35) return false;
+  // acceptance mode always takes 16 right-hand sides per pass
+  if (P.accept) pl = 2;
   const size_t dyn =
       ((size_t)8 * 2 * P.M + (size_t)3 * P.n * (P.l + 1)) * sizeof(double);
-#define ORBF_REG_CASE(LL, PP)                                                \
-  if (P.K <= 8 * LL) {                                                       \
-    if (P.accept)                                                            \
-      hipLaunchKernelGGL((weights_reg_kernel<LL, PP, true>),                 \
-                         dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P); \
-    else                                                                     \
-      hipLaunchKernelGGL((weights_reg_kernel<LL, PP, false>),                \
-                         dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P); \
-    return true;                                                             \
+#define ORBF_REG_CASE(LL)                                                     \
+  if (P.K <= 8 * LL) {                                                        \
+    if (P.accept)                                                             \
+      hipLaunchKernelGGL((weights_reg_kernel<LL, 2, true>),                   \
+                         dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P);  \
+    else if (pl == 1)                                                         \
+      hipLaunchKernelGGL((weights_reg_kernel<LL, 1, false>),                  \
+                         dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P);  \
+    else                                                                      \
+      hipLaunchKernelGGL((weights_reg_kernel<LL, 2, false>),                  \
+                         dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P);  \
+    return true;                                                              \
   }
-  ORBF_REG_CASE(3, 2)
-  ORBF_REG_CASE(4, 2)
-  ORBF_REG_CASE(5, 2)
-  ORBF_REG_CASE(6, 2)
-  ORBF_REG_CASE(7, 2)
-  ORBF_REG_CASE(8, 2)
-  ORBF_REG_CASE(9, 2)
+  ORBF_REG_CASE(3)
+  ORBF_REG_CASE(4)
+  ORBF_REG_CASE(5)
+  ORBF_REG_CASE(6)
+  ORBF_REG_CASE(7)
+  ORBF_REG_CASE(8)
+  ORBF_REG_CASE(9)
 #undef ORBF_REG_CASE
   return false;
 }

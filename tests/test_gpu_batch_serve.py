@@ -240,3 +240,40 @@ def test_server_and_batch_errors(orbf):
     with pytest.raises(orbf.OrbfError) as e:
         orbf.build_dm_batched(ctx, [dict(xyz=x, n=8, m=3, l=2, delta=1.5)])
     assert e.value.code == orbf.EINVAL
+
+
+def test_schedules_and_tuner(orbf):
+    """Every schedule gives the oracle's weights (the two one-wavefront
+    schedules bit for bit alike); the table rejects what a kernel cannot
+    serve; the tuner picks one candidate per (K, p-class)."""
+    from paper_1606_03135_amd import tune
+    ctx = orbf.Context(0)
+    x = nodesets.ball(6000, 2)["x"]
+    xd = gpu(x)
+    n, m, l, delta = 50, 5, 3, 0.3  # K = 70
+    K = n + 20
+    pc = tune.pclass(n, 3, delta)
+    ref = oracle.build_dm(x, n, m, l, delta)
+    own = ref["owner"] >= 0
+    out = {}
+    for name in ("wave16", "wave8", "group16"):
+        tune.set_schedule(ctx, K, pc, name)
+        r = orbf.build_dm(xd, n, m, l, delta, ctx=ctx)
+        W = r["W"].cpu().numpy()
+        err = float((np.abs(W[own] - ref["W"][own]).max(1) /
+                     np.abs(ref["W"][own]).max(1)).max())
+        _say(f"[gpu] schedule {name}: max row rel err {err:.2e}")
+        assert err <= 1e-9
+        out[name] = r["W"]
+    assert torch.equal(out["wave16"], out["wave8"])
+    assert (K, pc, "group16") in tune.get_schedules(ctx)
+    with pytest.raises(orbf.OrbfError):
+        tune.set_schedule(ctx, 100, 0, "wave16")  # K > 72
+    tune.set_schedule(ctx, K, pc, None)
+    assert tune.get_schedules(ctx) == []
+    specs = small_specs(6, 21, nmax=4000)
+    sets = [as_set(s, nodesets.make_set(s)) for s in specs]
+    rep, secs = tune.tune_sets(ctx, sets, reps=2)
+    _say(f"[gpu] tuner: {len(rep)} classes in {secs:.1f} s")
+    assert {(r["K"], r["pclass"]) for r in rep} == {
+        (K_, p_) for K_, p_, _ in tune.get_schedules(ctx)}
