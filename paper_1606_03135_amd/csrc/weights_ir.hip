@@ -140,6 +140,9 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
       });
     });
 
+    // every row slot starts unranked (see the zero-pivot fallback below)
+    for (int t = lane; t < S; t += 64) srank[t] = 1 << 20;
+    wsync();
     // ---- FP32 Gauss-Jordan, multipliers kept in place ----
     uint32_t act[L];
     sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
@@ -226,9 +229,9 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
     float rdk[L];
     sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
       constexpr int ii = decltype(iic)::value;
-      const bool live = 8 * ii + r < K;
-      rank[ii] = live ? srank[8 * ii + r] : 1 << 20;
-      rdk[ii] = live ? dinv_s[rank[ii]] : 0.0f;
+      const int sr = (8 * ii + r < K) ? srank[8 * ii + r] : 1 << 20;
+      rank[ii] = ((unsigned)sr < (unsigned)K) ? sr : 1 << 20;
+      rdk[ii] = ((unsigned)sr < (unsigned)K) ? dinv_s[sr] : 0.0f;
     });
     bool ok = !zero_pivot;
 
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
         sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
           constexpr int ii = decltype(iic)::value;
           const int j = rank[ii];
-          if (live && j < n) {
+          if (live && (unsigned)j < (unsigned)n) {
             const double w = X[ii][jp] * sinv;
             P.W[(int64_t)row * n + j] = w;
             lam += fabs(w);

@@ -240,6 +240,10 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
           a[ii][jj] = strip[jj * 64 + lane];
         });
       });
+      // every row slot starts unranked: a slot no step pivots (possible
+      // only for an exactly singular system) must not index anything
+      for (int t = lane; t < S; t += 64) srank[t] = 1 << 20;
+      wsync();
       // ---- LU with row partial pivoting, rows kept in place ----
       // act[ii]: magnitude mask of local row ii (0 once the row has been
       // used as a pivot).  Pivoted rows keep their U entries and receive
@@ -331,9 +335,9 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
       double rdk[L];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
         constexpr int ii = decltype(iic)::value;
-        const bool live = 8 * ii + r < K;
-        rank[ii] = live ? srank[8 * ii + r] : 1 << 20;
-        rdk[ii] = live ? dinv[rank[ii]] : 0.0;
+        const int sr = (8 * ii + r < K) ? srank[8 * ii + r] : 1 << 20;
+        rank[ii] = ((unsigned)sr < (unsigned)K) ? sr : 1 << 20;
+        rdk[ii] = ((unsigned)sr < (unsigned)K) ? dinv[sr] : 0.0;
       });
       // ---- unscale, write rows, Lebesgue values ----
       // row slot with rank j holds the unknown x_j; weights are x_j, j < n
@@ -347,7 +351,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
           constexpr int ii = decltype(iic)::value;
           const int j = rank[ii];
-          if (live && j < n) {
+          if (live && (unsigned)j < (unsigned)n) {
             const double w = singular ? NAN : (a[ii][L + jp] * rdk[ii]) * sinv;
             if (!accept_mode) P.W[(int64_t)row * n + j] = w;
             lam += fabs(w);
@@ -356,6 +360,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         lam += __shfl_xor(lam, 1, 64);
         lam += __shfl_xor(lam, 2, 64);
         lam += __shfl_xor(lam, 4, 64);
+        if (singular) lam = NAN;
         if (live && r == 0) {
           if (accept_mode) {
             lam_s[cb + e] = lam;
@@ -365,6 +370,14 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
           }
         }
       });
+      if (singular && !accept_mode) {
+        // a singular system ranks some slot twice and another never: write
+        // every weight of its rows as NaN rather than trust the ranks
+        for (int t = lane; t < nb * n; t += 64) {
+          const int e = t / n, q = t - e * n;
+          P.W[(int64_t)stn[cols_s[cb + e]] * n + q] = NAN;
+        }
+      }
       wsync();
     }
     if (accept_mode) {

@@ -181,6 +181,10 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
           a[ii][jj] = strip[jj * kThreads + t];
         });
       });
+      // every row slot starts unranked: a slot no step pivots (possible
+      // only for an exactly singular system) must not index anything
+      for (int q = t; q < S; q += kThreads) srank[q] = 1 << 20;
+      __syncthreads();
       // ---- partial pivoting, rows in place, Gauss-Jordan sweep ----
       uint32_t act[L];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
@@ -268,9 +272,9 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
       double rdk[L];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
         constexpr int ii = decltype(iic)::value;
-        const bool live = kG * ii + r < K;
-        rank[ii] = live ? srank[kG * ii + r] : 1 << 20;
-        rdk[ii] = live ? dinv[rank[ii]] : 0.0;
+        const int sr = (kG * ii + r < K) ? srank[kG * ii + r] : 1 << 20;
+        rank[ii] = ((unsigned)sr < (unsigned)K) ? sr : 1 << 20;
+        rdk[ii] = ((unsigned)sr < (unsigned)K) ? dinv[sr] : 0.0;
       });
       if (singular && t == 0) report(P.st, ORBF_ESINGULAR, ck);
       // ---- unscale, write rows, Lebesgue values ----
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
         sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
           constexpr int ii = decltype(iic)::value;
           const int j = rank[ii];
-          if (live && j < n) {
+          if (live && (unsigned)j < (unsigned)n) {
             const double w =
                 singular ? NAN : (a[ii][L + jp] * rdk[ii]) * sinv;
             P.W[(int64_t)row * n + j] = w;
@@ -294,11 +298,20 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
         lam += __shfl_xor(lam, 2, 64);
         lam += __shfl_xor(lam, 4, 64);
         lam += __shfl_xor(lam, 8, 64);
+        if (singular) lam = NAN;
         if (live && r == 0) {
           if (P.lebesgue) P.lebesgue[row] = lam;
           if (explicit_rows && P.owner_out) P.owner_out[row] = row;
         }
       });
+      if (singular) {
+        // a singular system ranks some slot twice and another never: write
+        // every weight of its rows as NaN rather than trust the ranks
+        for (int q = t; q < nb * n; q += kThreads) {
+          const int e = q / n, s2 = q - e * n;
+          P.W[(int64_t)stn[cols_s[cb + e]] * n + s2] = NAN;
+        }
+      }
     }
     __syncthreads();
   }

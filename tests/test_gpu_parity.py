@@ -344,3 +344,23 @@ def test_cover_recorded_distances_match_gathered(orbf, ctx):
         assert nc == int(nb.item())
         assert torch.equal(oa, ob)
         assert torch.equal(ca[:nc], cb[:nc]) and torch.equal(pa[:nc], pb[:nc])
+
+
+@pytest.mark.parametrize("n,l,prec", [(12, 2, 0), (12, 2, 1), (70, 4, 0)])
+def test_singular_stencils(orbf, n, l, prec):
+    """Nodes on a line in 2D: the monomials in y vanish, every stencil
+    system is exactly singular.  The build must report ESINGULAR at sync
+    and leave NaN rows (one-wavefront kernel, its FP32 form, and the
+    four-wavefront kernel for K = 85)."""
+    ctx = orbf.Context(0)
+    N = 200
+    x = np.zeros((N, 2))
+    x[:, 0] = (np.arange(N) + 0.5) / N
+    _say(f"[gpu] singular line N={N} n={n} l={l} prec={prec}")
+    r = orbf.build_dm(gpu(x), n, 3 if l == 2 else 5, l, 1.0, ctx=ctx,
+                      sync=False, prec=prec)
+    with pytest.raises(orbf.OrbfError) as e:
+        ctx.sync()
+    assert e.value.code == orbf.ESINGULAR
+    W = r["W"].cpu().numpy()
+    assert np.isnan(W).all()
