@@ -235,6 +235,7 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   t += want(scan_tmp_elems((int64_t)Nn + 66) * 8);  // B_SCAN_TMP
   t += want(Nn * 4) + want(8);          // B_IR_FALLBACK, B_IR_COUNT
   t += want(Nn * (size_t)n * 8);        // B_KNN_D2
+  t += want(Nn * (size_t)n);            // B_CSR_RANK
   return t;
 }
 

@@ -1,8 +1,8 @@
 // Sparse DM in CSR (Sec. 4.1: L(R^k_i, I^k_j) = W^{phi,k}_{j,i}).
 // Row pointers are a prefix sum of the row lengths (n for every row with an
-// owner).  One wavefront per row ranks the n stencil indices of the owner's
-// stencil (all distinct) by a wave-wide comparison and writes each (index,
-// weight) pair at its rank, so every row is written with coalesced stores.
+// owner).  Each stencil's n indices (all distinct) are ranked once, by the
+// wavefront of the row that owns itself (its center, or an explicit row);
+// then one wavefront per row writes each (index, weight) pair at its rank.
 #include "orbf_internal.hpp"
 
 namespace orbf {
@@ -16,12 +16,44 @@ __global__ __launch_bounds__(256) void row_len_kernel(
   if (e < N) len[e] = owner[e] >= 0 ? n : 0;
 }
 
+// Rank of every stencil position within its stencil, once per stencil: a
+// wavefront per node that owns its own row (centers, explicit rows).
+template <int PER_LANE>
+__global__ __launch_bounds__(256) void stencil_rank_kernel(
+    const int32_t* __restrict__ knn, const int32_t* __restrict__ owner,
+    int64_t N, int n, uint8_t* __restrict__ crank) {
+  const int lane = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= N || owner[e] != e) return;  // whole wavefront
+  int32_t idx[PER_LANE];
+#pragma unroll
+  for (int h = 0; h < PER_LANE; ++h) {
+    const int q = lane + 64 * h;
+    idx[h] = q < n ? knn[e * n + q] : INT32_MAX;
+  }
+  int rank[PER_LANE];
+#pragma unroll
+  for (int h = 0; h < PER_LANE; ++h) rank[h] = 0;
+#pragma unroll
+  for (int g = 0; g < PER_LANE; ++g) {
+    for (int s = 0; s < 64; ++s) {
+      const int32_t v = __shfl(idx[g], s, 64);
+#pragma unroll
+      for (int h = 0; h < PER_LANE; ++h) rank[h] += v < idx[h];
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < PER_LANE; ++h)
+    if (lane + 64 * h < n) crank[e * n + lane + 64 * h] = (uint8_t)rank[h];
+}
+
+// Row e: the owner's stencil at the recorded ranks, with row e's weights.
 template <int PER_LANE>
 __global__ __launch_bounds__(256) void csr_scatter_kernel(
     const int32_t* __restrict__ knn, const int32_t* __restrict__ owner,
-    const double* __restrict__ W, int64_t N, int n,
-    const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
-    double* __restrict__ val) {
+    const double* __restrict__ W, const uint8_t* __restrict__ crank,
+    int64_t N, int n, const int64_t* __restrict__ row_ptr,
+    int32_t* __restrict__ col, double* __restrict__ val) {
   const int lane = threadIdx.x & 63;
   for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < N;
        e += (int64_t)gridDim.x * 4) {
@@ -36,22 +68,13 @@ __global__ __launch_bounds__(256) void csr_scatter_kernel(
       idx[h] = q < n ? knn[(int64_t)o * n + q] : INT32_MAX;
       w[h] = q < n ? W[e * n + q] : 0.0;
     }
-    int rank[PER_LANE];
-#pragma unroll
-    for (int h = 0; h < PER_LANE; ++h) rank[h] = 0;
-#pragma unroll
-    for (int g = 0; g < PER_LANE; ++g) {
-      for (int s = 0; s < 64; ++s) {
-        const int32_t v = __shfl(idx[g], s, 64);
-#pragma unroll
-        for (int h = 0; h < PER_LANE; ++h) rank[h] += v < idx[h];
-      }
-    }
 #pragma unroll
     for (int h = 0; h < PER_LANE; ++h) {
-      if (lane + 64 * h < n) {
-        col[base + rank[h]] = idx[h];
-        val[base + rank[h]] = w[h];
+      const int q = lane + 64 * h;
+      if (q < n) {
+        const int rk = crank[(int64_t)o * n + q];
+        col[base + rk] = idx[h];
+        val[base + rk] = w[h];
       }
     }
   }
@@ -64,6 +87,7 @@ orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        int64_t* row_ptr, int32_t* col, double* val) {
   orbf_status st = ORBF_OK;
   auto* len = (int32_t*)scratch(ctx, B_INDEG, (size_t)(N + 1) * 4, &st);
+  auto* crank = (uint8_t*)scratch(ctx, B_CSR_RANK, (size_t)N * n, &st);
   if (st) return st;
   hipStream_t s = ctx->stream;
   const unsigned g = (unsigned)((N + 255) / 256);
@@ -72,12 +96,18 @@ orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
   if (st) return st;
   const int64_t blocks = (N + 3) / 4;
   const dim3 grid((unsigned)(blocks < (1 << 20) ? blocks : (1 << 20)));
-  if (n <= 64)
+  const dim3 rgrid((unsigned)blocks);  // one wavefront per node
+  if (n <= 64) {
+    hipLaunchKernelGGL(stencil_rank_kernel<1>, rgrid, dim3(256), 0, s, knn,
+                       owner, N, n, crank);
     hipLaunchKernelGGL(csr_scatter_kernel<1>, grid, dim3(256), 0, s, knn,
-                       owner, W, N, n, row_ptr, col, val);
-  else
+                       owner, W, crank, N, n, row_ptr, col, val);
+  } else {
+    hipLaunchKernelGGL(stencil_rank_kernel<2>, rgrid, dim3(256), 0, s, knn,
+                       owner, N, n, crank);
     hipLaunchKernelGGL(csr_scatter_kernel<2>, grid, dim3(256), 0, s, knn,
-                       owner, W, N, n, row_ptr, col, val);
+                       owner, W, crank, N, n, row_ptr, col, val);
+  }
   return hip_check(ctx, hipGetLastError(), "csr");
 }
 

@@ -83,7 +83,7 @@ struct orbf_ctx {
   std::string err;
   orbf::DevStatus* status = nullptr;  // device
   orbf::DevStatus* status_host = nullptr;  // pinned mirror
-  orbf::Buffer buf[32];
+  orbf::Buffer buf[32];  // indexed by BufId
   int num_cus = 256;
   hipEvent_t ev[10] = {};
   bool timing = true;  // record phase events (off on batch/serving workers)
@@ -138,7 +138,10 @@ enum BufId {
   B_IR_FALLBACK,
   B_IR_COUNT,
   B_KNN_D2,
+  B_CSR_RANK,
+  B_NUM,
 };
+static_assert(B_NUM <= 32, "orbf_ctx::buf holds 32 scratch buffers");
 
 // ctx helpers (api.hip)
 orbf_status fail(orbf_ctx* ctx, orbf_status code, const std::string& msg);
