@@ -57,6 +57,9 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
   double* pw_s = lpsi_s + NB * M;
   double* strip = xs;
   for (int t = lane; t < 3 * M; t += 64) ex_s[t] = P.ex[t];
+  // eliminations write only values in [0, K) here, so with this start no
+  // rank read below can index out of range
+  for (int t = lane; t < S; t += 64) srank[t] = 0;
 
   const int64_t total = *P.n_centers;
   for (int64_t ci = blockIdx.x; ci < total; ci += gridDim.x) {
@@ -140,9 +143,6 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
       });
     });
 
-    // every row slot starts unranked (see the zero-pivot fallback below)
-    for (int t = lane; t < S; t += 64) srank[t] = 1 << 20;
-    wsync();
     // ---- FP32 Gauss-Jordan, multipliers kept in place ----
     uint32_t act[L];
     sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
@@ -225,13 +225,16 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
       }
     });
 
+    // Without a zero pivot every step pivots a row still active, so each
+    // of the K slots has exactly one rank; with one, the ranks are not used
+    // (the stencil goes to the FP64 fallback).
     int rank[L];
     float rdk[L];
     sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
       constexpr int ii = decltype(iic)::value;
-      const int sr = (8 * ii + r < K) ? srank[8 * ii + r] : 1 << 20;
-      rank[ii] = ((unsigned)sr < (unsigned)K) ? sr : 1 << 20;
-      rdk[ii] = ((unsigned)sr < (unsigned)K) ? dinv_s[sr] : 0.0f;
+      const bool live = 8 * ii + r < K;
+      rank[ii] = live ? srank[8 * ii + r] : 1 << 20;
+      rdk[ii] = live ? dinv_s[rank[ii]] : 0.0f;
     });
     bool ok = !zero_pivot;
 
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
         sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
           constexpr int ii = decltype(iic)::value;
           const int j = rank[ii];
-          if (live && (unsigned)j < (unsigned)n) {
+          if (live && j < n) {
             const double w = X[ii][jp] * sinv;
             P.W[(int64_t)row * n + j] = w;
             lam += fabs(w);

@@ -62,6 +62,9 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
   double* lpsi_s = dyn_s;               // L psi_t at the evaluation points
   double* pw_s = lpsi_s + 8 * PL * M;   // powers of the scaled coordinates
   for (int t = lane; t < 3 * M; t += 64) ex_s[t] = P.ex[t];
+  // every elimination writes only values in [0, K) here, so with this
+  // start no rank read below can ever index out of range
+  for (int t = lane; t < S; t += 64) srank[t] = 0;
 
   const bool explicit_rows = P.rows != nullptr;
   const int64_t total = explicit_rows ? P.n_rows : *P.n_centers;
@@ -240,10 +243,6 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
           a[ii][jj] = strip[jj * 64 + lane];
         });
       });
-      // every row slot starts unranked: a slot no step pivots (possible
-      // only for an exactly singular system) must not index anything
-      for (int t = lane; t < S; t += 64) srank[t] = 1 << 20;
-      wsync();
       // ---- LU with row partial pivoting, rows kept in place ----
       // act[ii]: magnitude mask of local row ii (0 once the row has been
       // used as a pivot).  Pivoted rows keep their U entries and receive
@@ -331,13 +330,22 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         }
       });
       // ---- solution: the row slot pivoted at step j holds u_jj x_j ----
+      // Every step of a nonsingular system pivots a row still active, so
+      // each of the K slots gets exactly one rank.  A singular system may
+      // rank one slot twice and leave another with a stale rank; its slots
+      // are then mapped to themselves, which writes each of its weights
+      // exactly once, as NaN (and so makes Lambda NaN too).
+      if (singular) {
+        for (int t = lane; t < S; t += 64) srank[t] = t;
+        wsync();
+      }
       int rank[L];
       double rdk[L];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
         constexpr int ii = decltype(iic)::value;
-        const int sr = (8 * ii + r < K) ? srank[8 * ii + r] : 1 << 20;
-        rank[ii] = ((unsigned)sr < (unsigned)K) ? sr : 1 << 20;
-        rdk[ii] = ((unsigned)sr < (unsigned)K) ? dinv[sr] : 0.0;
+        const bool live = 8 * ii + r < K;
+        rank[ii] = live ? srank[8 * ii + r] : 1 << 20;
+        rdk[ii] = live ? dinv[rank[ii]] : 0.0;
       });
       // ---- unscale, write rows, Lebesgue values ----
       // row slot with rank j holds the unknown x_j; weights are x_j, j < n
@@ -351,7 +359,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
           constexpr int ii = decltype(iic)::value;
           const int j = rank[ii];
-          if (live && (unsigned)j < (unsigned)n) {
+          if (live && j < n) {
             const double w = singular ? NAN : (a[ii][L + jp] * rdk[ii]) * sinv;
             if (!accept_mode) P.W[(int64_t)row * n + j] = w;
             lam += fabs(w);
@@ -360,7 +368,6 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         lam += __shfl_xor(lam, 1, 64);
         lam += __shfl_xor(lam, 2, 64);
         lam += __shfl_xor(lam, 4, 64);
-        if (singular) lam = NAN;
         if (live && r == 0) {
           if (accept_mode) {
             lam_s[cb + e] = lam;
@@ -370,14 +377,6 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
           }
         }
       });
-      if (singular && !accept_mode) {
-        // a singular system ranks some slot twice and another never: write
-        // every weight of its rows as NaN rather than trust the ranks
-        for (int t = lane; t < nb * n; t += 64) {
-          const int e = t / n, q = t - e * n;
-          P.W[(int64_t)stn[cols_s[cb + e]] * n + q] = NAN;
-        }
-      }
       wsync();
     }
     if (accept_mode) {

@@ -61,6 +61,9 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
   double* pw_s = lpsi_s + kG * PL * M;
   double* strip = pw_s + 3 * n * l1;
   for (int q = t; q < 3 * M; q += kThreads) ex_s[q] = P.ex[q];
+  // eliminations write only values in [0, K) here, so with this start no
+  // rank read below can index out of range
+  for (int q = t; q < S; q += kThreads) srank[q] = 0;
 
   const bool explicit_rows = P.rows != nullptr;
   const int64_t total = explicit_rows ? P.n_rows : *P.n_centers;
@@ -181,10 +184,6 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
           a[ii][jj] = strip[jj * kThreads + t];
         });
       });
-      // every row slot starts unranked: a slot no step pivots (possible
-      // only for an exactly singular system) must not index anything
-      for (int q = t; q < S; q += kThreads) srank[q] = 1 << 20;
-      __syncthreads();
       // ---- partial pivoting, rows in place, Gauss-Jordan sweep ----
       uint32_t act[L];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
@@ -268,13 +267,23 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
         }
       });
       __syncthreads();
+      // Every step of a nonsingular system pivots a row still active, so
+      // each of the K slots gets exactly one rank.  A singular system may
+      // rank one slot twice and leave another with a stale rank; its slots
+      // are then mapped to themselves, which writes each of its weights
+      // exactly once, as NaN (and so makes Lambda NaN too).  The flag comes
+      // from LDS, so the branch is uniform over the workgroup.
+      if (singular) {
+        for (int q = t; q < S; q += kThreads) srank[q] = q;
+        __syncthreads();
+      }
       int rank[L];
       double rdk[L];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
         constexpr int ii = decltype(iic)::value;
-        const int sr = (kG * ii + r < K) ? srank[kG * ii + r] : 1 << 20;
-        rank[ii] = ((unsigned)sr < (unsigned)K) ? sr : 1 << 20;
-        rdk[ii] = ((unsigned)sr < (unsigned)K) ? dinv[sr] : 0.0;
+        const bool live = kG * ii + r < K;
+        rank[ii] = live ? srank[kG * ii + r] : 1 << 20;
+        rdk[ii] = live ? dinv[rank[ii]] : 0.0;
       });
       if (singular && t == 0) report(P.st, ORBF_ESINGULAR, ck);
       // ---- unscale, write rows, Lebesgue values ----
@@ -287,7 +296,7 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
         sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
           constexpr int ii = decltype(iic)::value;
           const int j = rank[ii];
-          if (live && (unsigned)j < (unsigned)n) {
+          if (live && j < n) {
             const double w =
                 singular ? NAN : (a[ii][L + jp] * rdk[ii]) * sinv;
             P.W[(int64_t)row * n + j] = w;
@@ -298,20 +307,11 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
         lam += __shfl_xor(lam, 2, 64);
         lam += __shfl_xor(lam, 4, 64);
         lam += __shfl_xor(lam, 8, 64);
-        if (singular) lam = NAN;
         if (live && r == 0) {
           if (P.lebesgue) P.lebesgue[row] = lam;
           if (explicit_rows && P.owner_out) P.owner_out[row] = row;
         }
       });
-      if (singular) {
-        // a singular system ranks some slot twice and another never: write
-        // every weight of its rows as NaN rather than trust the ranks
-        for (int q = t; q < nb * n; q += kThreads) {
-          const int e = q / n, s2 = q - e * n;
-          P.W[(int64_t)stn[cols_s[cb + e]] * n + s2] = NAN;
-        }
-      }
     }
     __syncthreads();
   }
