@@ -346,34 +346,42 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
       const double guess = est > 0.0 ? est * kGrow : g.s * g.s;
       double T = guess < cut ? guess : cut;
       for (int it = 0; it < 64; ++it) {
-        // one pass: compact every candidate with d^2 < T
+        // one pass: compact every candidate with d^2 < T.  A row of cells
+        // (fixed y, z) is contiguous in cell order and holds a few dozen
+        // nodes, so each half-wavefront scans one row: two rows per step.
         int base = 0;
-        for (int z = lo2; z <= hi2; ++z)
-          for (int y = lo1; y <= hi1; ++y) {
+        const int ny = hi1 - lo1 + 1;
+        const int rows = ny * (hi2 - lo2 + 1);
+        const int half = lane >> 5, hl = lane & 31;
+        for (int pr = 0; pr < rows; pr += 2) {
+          const int row = pr + half;
+          int64_t s0 = 0, s1 = 0;
+          if (row < rows) {
+            const int z = lo2 + row / ny, y = lo1 + row % ny;
             const int64_t crow = ((int64_t)z * g.nc[1] + y) * g.nc[0];
-            const int64_t s0 = cstart[crow + lo0];
-            const int64_t s1 = cstart[crow + hi0 + 1];
-            for (int64_t t0 = s0; t0 < s1; t0 += 64) {
-              const int64_t t = t0 + lane;
-              bool keep = false;
-              double d2 = 0.0;
-              if (t < s1) {
-                const double* p = xs + t * d;
-                d2 = exact_sqdist(q0, q1, q2, p[0], p[1], d == 3 ? p[2] : 0.0, d);
-                if (d2 == 0.0 && t != qs) dup = true;
-                keep = d2 < T;
-              }
-              const unsigned long long m = __ballot(keep);
-              if (keep) {
-                const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-                if (pos < kKeep) {
-                  kd[w][pos] = d2;
-                  kj[w][pos] = perm[t];
-                }
-              }
-              base += __popcll(m);
-            }
+            s0 = cstart[crow + lo0];
+            s1 = cstart[crow + hi0 + 1];
           }
+          for (int64_t t = s0 + hl; __ballot(t < s1) != 0ull; t += 32) {
+            bool keep = false;
+            double d2 = 0.0;
+            if (t < s1) {
+              const double* p = xs + t * d;
+              d2 = exact_sqdist(q0, q1, q2, p[0], p[1], d == 3 ? p[2] : 0.0, d);
+              if (d2 == 0.0 && t != qs) dup = true;
+              keep = d2 < T;
+            }
+            const unsigned long long m = __ballot(keep);
+            if (keep) {
+              const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+              if (pos < kKeep) {
+                kd[w][pos] = d2;
+                kj[w][pos] = perm[t];
+              }
+            }
+            base += __popcll(m);
+          }
+        }
         if (base < n) {
           if (T >= cut) break;  // too few inside the provable radius: grow R
           tlo = T;
