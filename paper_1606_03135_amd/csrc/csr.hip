@@ -2,7 +2,7 @@
 // Row pointers are a prefix sum of the row lengths (n for every row with an
 // owner).  Each stencil's n indices (all distinct) are ranked once, by the
 // wavefront of the row that owns itself (its center, or an explicit row);
-// then one wavefront per row writes each (index, weight) pair at its rank.
+// then one thread per entry writes each (index, weight) pair at its rank.
 #include "orbf_internal.hpp"
 
 namespace orbf {
@@ -48,35 +48,24 @@ __global__ __launch_bounds__(256) void stencil_rank_kernel(
 }
 
 // Row e: the owner's stencil at the recorded ranks, with row e's weights.
-template <int PER_LANE>
+// A block step covers rpb = 256 / n whole rows, one thread per entry, so
+// loads of W and stores of col/val stream through contiguous rows.
 __global__ __launch_bounds__(256) void csr_scatter_kernel(
     const int32_t* __restrict__ knn, const int32_t* __restrict__ owner,
     const double* __restrict__ W, const uint8_t* __restrict__ crank,
-    int64_t N, int n, const int64_t* __restrict__ row_ptr,
+    int64_t N, int n, int rpb, const int64_t* __restrict__ row_ptr,
     int32_t* __restrict__ col, double* __restrict__ val) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); e < N;
-       e += (int64_t)gridDim.x * 4) {
+  const int t = threadIdx.x;
+  const int rl = t / n, q = t - rl * n;
+  if (rl >= rpb) return;
+  for (int64_t e = (int64_t)blockIdx.x * rpb + rl; e < N;
+       e += (int64_t)gridDim.x * rpb) {
     const int32_t o = owner[e];
     if (o < 0 || o >= N) continue;
-    const int64_t base = row_ptr[e];
-    int32_t idx[PER_LANE];
-    double w[PER_LANE];
-#pragma unroll
-    for (int h = 0; h < PER_LANE; ++h) {
-      const int q = lane + 64 * h;
-      idx[h] = q < n ? knn[(int64_t)o * n + q] : INT32_MAX;
-      w[h] = q < n ? W[e * n + q] : 0.0;
-    }
-#pragma unroll
-    for (int h = 0; h < PER_LANE; ++h) {
-      const int q = lane + 64 * h;
-      if (q < n) {
-        const int rk = crank[(int64_t)o * n + q];
-        col[base + rk] = idx[h];
-        val[base + rk] = w[h];
-      }
-    }
+    const int64_t so = (int64_t)o * n + q;
+    const int64_t at = row_ptr[e] + crank[so];
+    col[at] = knn[so];
+    val[at] = W[e * n + q];
   }
 }
 
@@ -95,19 +84,18 @@ orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
   st = exclusive_scan_i32_to_i64(ctx, len, N, row_ptr);
   if (st) return st;
   const int64_t blocks = (N + 3) / 4;
-  const dim3 grid((unsigned)(blocks < (1 << 20) ? blocks : (1 << 20)));
   const dim3 rgrid((unsigned)blocks);  // one wavefront per node
-  if (n <= 64) {
+  if (n <= 64)
     hipLaunchKernelGGL(stencil_rank_kernel<1>, rgrid, dim3(256), 0, s, knn,
                        owner, N, n, crank);
-    hipLaunchKernelGGL(csr_scatter_kernel<1>, grid, dim3(256), 0, s, knn,
-                       owner, W, crank, N, n, row_ptr, col, val);
-  } else {
+  else
     hipLaunchKernelGGL(stencil_rank_kernel<2>, rgrid, dim3(256), 0, s, knn,
                        owner, N, n, crank);
-    hipLaunchKernelGGL(csr_scatter_kernel<2>, grid, dim3(256), 0, s, knn,
-                       owner, W, crank, N, n, row_ptr, col, val);
-  }
+  const int rpb = 256 / n;  // n <= 128
+  const int64_t steps = (N + rpb - 1) / rpb;
+  const dim3 grid((unsigned)(steps < (1 << 16) ? steps : (1 << 16)));
+  hipLaunchKernelGGL(csr_scatter_kernel, grid, dim3(256), 0, s, knn, owner, W,
+                     crank, N, n, rpb, row_ptr, col, val);
   return hip_check(ctx, hipGetLastError(), "csr");
 }
 
