@@ -107,17 +107,67 @@ __global__ __launch_bounds__(256) void ball_d2_kernel(
   }
 }
 
+// The same for n <= 64 with four nodes per wavefront, sixteen lanes per
+// node and four stencil positions per lane: each wavefront has four nodes'
+// dependent loads and all their in-degree updates in flight at once.
+__global__ __launch_bounds__(256) void ball_d2_quad_kernel(
+    const double* __restrict__ d2s, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ knn, const double* __restrict__ rho2,
+    int64_t N, int n, double t2, const uint8_t* __restrict__ eligible,
+    uint64_t* __restrict__ ball, int32_t* __restrict__ indeg,
+    int32_t* __restrict__ state, int32_t s_open, int32_t s_inel) {
+  const int lane = threadIdx.x & 63, part = lane >> 4, pl = lane & 15;
+  const int64_t qs = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 6) * 4 + part;
+  const bool valid = qs < N;  // no early return: the ballots need every lane
+  int64_t c = 0;
+  bool ec = false;
+  double thr = 0.0;
+  if (valid) {
+    c = perm[qs];
+    ec = eligible == nullptr || eligible[c] != 0;
+    thr = t2 * rho2[c];
+  }
+  uint64_t bw[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = pl + 16 * i;
+    bool in = false;
+    if (ec && q >= 1 && q < n) {
+      const double dq = d2s[qs * n + q];
+      const int32_t j = knn[c * n + q];
+      if (j > c && j < N && (eligible == nullptr || eligible[j] != 0) &&
+          dq <= thr) {
+        in = true;
+        atomicAdd(&indeg[j], 1);
+      }
+    }
+    bw[i] = __ballot(in);
+  }
+  if (valid && pl == 0) {
+    uint64_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m |= ((bw[i] >> (16 * part)) & 0xFFFFull) << (16 * i);
+    state[c] = ec ? s_open : s_inel;
+    ball[2 * c] = m;
+    ball[2 * c + 1] = 0ull;
+  }
+}
+
+// Predecessor lists: sixteen lanes per node, eight stencil positions per
+// lane (n <= 128), so all of a node's list insertions are in flight at once.
 __global__ __launch_bounds__(256) void pred_fill_kernel(
     const int32_t* __restrict__ knn, int64_t N, int n,
     const uint64_t* __restrict__ ball, const int64_t* __restrict__ start,
     int32_t* __restrict__ fill, int32_t* __restrict__ pred) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int pl = threadIdx.x & 15;
   if (c >= N) return;
-  for (int h = 0; h < 2; ++h) {
-    uint64_t b = ball[2 * c + h];
-    while (b) {
-      const int q = __ffsll((long long)b) - 1 + 64 * h;
-      b &= b - 1;
+  const uint64_t b0 = ball[2 * c], b1 = ball[2 * c + 1];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int q = pl + 16 * i;
+    const uint64_t b = q < 64 ? b0 : b1;
+    if (q < n && ((b >> (q & 63)) & 1ull)) {
       const int32_t j = knn[c * n + q];
       const int slot = atomicAdd(&fill[j], 1);
       pred[start[j] + slot] = (int32_t)c;
@@ -284,7 +334,12 @@ void launch_ball(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
                  const uint8_t* eligible, uint64_t* ball, int32_t* indeg,
                  int32_t* state, int32_t s_open, int32_t s_inel) {
   hipStream_t s = ctx->stream;
-  if (ctx->d2_cache.matches(xyz, knn, N, d, n)) {
+  if (ctx->d2_cache.matches(xyz, knn, N, d, n) && n <= 64) {
+    hipLaunchKernelGGL(ball_d2_quad_kernel, dim3((unsigned)((N + 15) / 16)),
+                       dim3(256), 0, s, ctx->d2_cache.d2, ctx->d2_cache.perm,
+                       knn, rho2, N, n, t2, eligible, ball, indeg, state,
+                       s_open, s_inel);
+  } else if (ctx->d2_cache.matches(xyz, knn, N, d, n)) {
     hipLaunchKernelGGL(ball_d2_kernel, dim3((unsigned)((N + 3) / 4)),
                        dim3(256), 0, s, ctx->d2_cache.d2, ctx->d2_cache.perm,
                        knn, rho2, N, n, t2, eligible, ball, indeg, state,
@@ -323,8 +378,8 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   const size_t max_edges = (size_t)N * (size_t)(n > 1 ? n - 1 : 1);
   auto* pred = (int32_t*)scratch(ctx, B_PRED, max_edges * 4, &st);
   if (st) return st;
-  hipLaunchKernelGGL(pred_fill_kernel, dim3(g), dim3(256), 0, s, knn, N, n,
-                     ball, pstart, fill, pred);
+  hipLaunchKernelGGL(pred_fill_kernel, dim3((unsigned)((N + 15) / 16)),
+                     dim3(256), 0, s, knn, N, n, ball, pstart, fill, pred);
   for (int r = 0; r < kRounds; ++r)
     hipLaunchKernelGGL(round_kernel, dim3(g), dim3(256), 0, s, pred, pstart, N,
                        state);
