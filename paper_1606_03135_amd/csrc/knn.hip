@@ -45,6 +45,29 @@ __device__ __forceinline__ bool key_less(double d, int j, double e, int k) {
   return d < e || (d == e && j < k);
 }
 
+// Value of lane ^ STRIDE.  Strides 1 and 2 are quad permutations and 8 is a
+// rotation by 8 within each 16-lane row, all DPP moves (VALU latency); the
+// others go through the LDS crossbar.  (Stride 4 from two rotations and a
+// select measured no faster than the crossbar.)
+template <int STRIDE>
+__device__ __forceinline__ int xor_lane(int v) {
+  if constexpr (STRIDE == 1)
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (STRIDE == 2)
+    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (STRIDE == 8)
+    return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+  else
+    return __shfl_xor(v, STRIDE, 64);
+}
+
+template <int STRIDE>
+__device__ __forceinline__ double xor_lane_f64(double v) {
+  const int lo = xor_lane<STRIDE>(__double2loint(v));
+  const int hi = xor_lane<STRIDE>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 // One compare-exchange stage of a bitonic sort over the elements
 // i = lane + 64 h held in registers (d[h], j[h]); partners at i ^ STRIDE
 // (STRIDE < 64: another lane, same register).
@@ -54,8 +77,8 @@ __device__ __forceinline__ void bitonic_stage(double (&d)[NR], int (&j)[NR],
 #pragma unroll
   for (int h = 0; h < NR; ++h) {
     const int i = lane + 64 * h;
-    const double pd = __shfl_xor(d[h], STRIDE, 64);
-    const int pj = __shfl_xor(j[h], STRIDE, 64);
+    const double pd = xor_lane_f64<STRIDE>(d[h]);
+    const int pj = xor_lane<STRIDE>(j[h]);
     const bool keep_min = ((i & STRIDE) == 0) == ((i & SIZE) == 0);
     const bool take = keep_min ? key_less(pd, pj, d[h], j[h])
                                : key_less(d[h], j[h], pd, pj);
