@@ -16,35 +16,43 @@ __global__ __launch_bounds__(256) void row_len_kernel(
   if (e < N) len[e] = owner[e] >= 0 ? n : 0;
 }
 
-// Rank of every stencil position within its stencil, once per stencil: a
-// wavefront per node that owns its own row (centers, explicit rows).
+// Rank of every stencil position within its stencil, once per stencil.
+// A wavefront reads the owners of 64 consecutive nodes in one load and
+// ranks, one after the other, the stencils of those that own themselves
+// (centers, explicit rows); lane q takes position q (and q + 64).
 template <int PER_LANE>
 __global__ __launch_bounds__(256) void stencil_rank_kernel(
     const int32_t* __restrict__ knn, const int32_t* __restrict__ owner,
     int64_t N, int n, uint8_t* __restrict__ crank) {
   const int lane = threadIdx.x & 63;
-  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (e >= N || owner[e] != e) return;  // whole wavefront
-  int32_t idx[PER_LANE];
+  const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+  if (e0 >= N) return;  // whole wavefront
+  const int64_t me = e0 + lane;
+  unsigned long long self = __ballot(me < N && owner[me] == me);
+  while (self) {
+    const int64_t e = e0 + __ffsll((long long)self) - 1;
+    self &= self - 1;
+    int32_t idx[PER_LANE];
 #pragma unroll
-  for (int h = 0; h < PER_LANE; ++h) {
-    const int q = lane + 64 * h;
-    idx[h] = q < n ? knn[e * n + q] : INT32_MAX;
-  }
-  int rank[PER_LANE];
-#pragma unroll
-  for (int h = 0; h < PER_LANE; ++h) rank[h] = 0;
-#pragma unroll
-  for (int g = 0; g < PER_LANE; ++g) {
-    for (int s = 0; s < 64; ++s) {
-      const int32_t v = __shfl(idx[g], s, 64);
-#pragma unroll
-      for (int h = 0; h < PER_LANE; ++h) rank[h] += v < idx[h];
+    for (int h = 0; h < PER_LANE; ++h) {
+      const int q = lane + 64 * h;
+      idx[h] = q < n ? knn[e * n + q] : INT32_MAX;
     }
-  }
+    int rank[PER_LANE];
 #pragma unroll
-  for (int h = 0; h < PER_LANE; ++h)
-    if (lane + 64 * h < n) crank[e * n + lane + 64 * h] = (uint8_t)rank[h];
+    for (int h = 0; h < PER_LANE; ++h) rank[h] = 0;
+#pragma unroll
+    for (int g = 0; g < PER_LANE; ++g) {
+      for (int s = 0; s < 64; ++s) {
+        const int32_t v = __shfl(idx[g], s, 64);
+#pragma unroll
+        for (int h = 0; h < PER_LANE; ++h) rank[h] += v < idx[h];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < PER_LANE; ++h)
+      if (lane + 64 * h < n) crank[e * n + lane + 64 * h] = (uint8_t)rank[h];
+  }
 }
 
 // Row e: the owner's stencil at the recorded ranks, with row e's weights.
@@ -83,8 +91,8 @@ orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
   hipLaunchKernelGGL(row_len_kernel, dim3(g), dim3(256), 0, s, owner, N, n, len);
   st = exclusive_scan_i32_to_i64(ctx, len, N, row_ptr);
   if (st) return st;
-  const int64_t blocks = (N + 3) / 4;
-  const dim3 rgrid((unsigned)blocks);  // one wavefront per node
+  // one wavefront per 64 nodes, four per block
+  const dim3 rgrid((unsigned)((N + 255) / 256));
   if (n <= 64)
     hipLaunchKernelGGL(stencil_rank_kernel<1>, rgrid, dim3(256), 0, s, knn,
                        owner, N, n, crank);
