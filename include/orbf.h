@@ -216,16 +216,26 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
  * at most 8, p-class 1 above (explicit rows are p-class 0).  The table is
  * filled by an autotuner that times the candidates (Python:
  * paper_1606_03135_amd.tune) and consulted by orbf_compute_weights; sizes
- * without an entry use WAVE16 for K <= 72 and GROUP16 up to 144.  Batched
- * builds pass the table to their workers. */
+ * without an entry use SPLIT for K <= 72 on N >= 65536 nodes (WAVE16 on
+ * fewer) and GROUP16 up to 144.  SPLIT takes each stencil's retained-row
+ * count from the covering when handed that covering's own centers and owner
+ * arrays (else it counts them, one extra pass over the stencils); the
+ * weights are the same bit for bit whatever the pass width.  Batched builds
+ * pass the table to their workers. */
 typedef enum orbf_schedule {
   ORBF_SCHED_DEFAULT = -1,
   ORBF_SCHED_WAVE16 = 0,  /* one wavefront per stencil, 16 right-hand sides
                              per pass (K <= 72)                              */
   ORBF_SCHED_WAVE8 = 1,   /* one wavefront, 8 right-hand sides per pass
                              (K <= 72): fewer registers                      */
-  ORBF_SCHED_GROUP16 = 2  /* four wavefronts on a 16 x 16 lane grid, 16
+  ORBF_SCHED_GROUP16 = 2, /* four wavefronts on a 16 x 16 lane grid, 16
                              right-hand sides per pass (K <= 144)            */
+  ORBF_SCHED_SPLIT = 3    /* one wavefront per stencil, with 8, 16 or 24
+                             right-hand sides per pass chosen per stencil
+                             from its retained-row count p (p <= 8, <= 16,
+                             above): stencils are sorted into three lists on
+                             the device and each list is one launch
+                             (K <= 72)                                       */
 } orbf_schedule;
 
 /* Set (or with ORBF_SCHED_DEFAULT clear) the schedule of (K, pclass).

@@ -65,6 +65,7 @@ void release_scratch(orbf_ctx* ctx) {
   }
   ctx->held = 0;
   ctx->d2_cache = D2Cache();
+  ctx->p_cache = PCache();
 }
 
 int schedule_for(const orbf_ctx* ctx, int K, int pclass) {
@@ -236,6 +237,8 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   t += want(Nn * 4) + want(8);          // B_IR_FALLBACK, B_IR_COUNT
   t += want(Nn * (size_t)n * 8);        // B_KNN_D2
   t += want(Nn * (size_t)n);            // B_CSR_RANK
+  t += want(Nn * 12) + want(24);        // B_CLASS, B_CLASS_N
+  t += want(Nn * 4);                    // B_P_CACHE
   return t;
 }
 
@@ -325,12 +328,13 @@ orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,
   if (!ctx) return ORBF_EINVAL;
   if (K < 1 || K > 160 || pclass < 0 || pclass > 1)
     return fail(ctx, ORBF_EINVAL, "schedule: K in 1..160, pclass 0 or 1");
-  if ((schedule == ORBF_SCHED_WAVE16 || schedule == ORBF_SCHED_WAVE8) &&
+  if ((schedule == ORBF_SCHED_WAVE16 || schedule == ORBF_SCHED_WAVE8 ||
+       schedule == ORBF_SCHED_SPLIT) &&
       K > 72)
     return fail(ctx, ORBF_EINVAL, "one-wavefront schedules need K <= 72");
   if (schedule == ORBF_SCHED_GROUP16 && K > 144)
     return fail(ctx, ORBF_EINVAL, "the workgroup schedule needs K <= 144");
-  if (schedule < ORBF_SCHED_DEFAULT || schedule > ORBF_SCHED_GROUP16)
+  if (schedule < ORBF_SCHED_DEFAULT || schedule > ORBF_SCHED_SPLIT)
     return fail(ctx, ORBF_EINVAL, "unknown schedule");
   auto& t = ctx->schedules;
   for (size_t i = 0; i + 2 < t.size(); i += 3)

@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void centers_kernel(
     const int32_t* __restrict__ knn, const uint64_t* __restrict__ ball,
     const int32_t* __restrict__ owner, int64_t N, int n,
     int32_t* __restrict__ centers, int32_t* __restrict__ p,
-    int64_t* __restrict__ n_centers) {
+    int32_t* __restrict__ p_keep, int64_t* __restrict__ n_centers) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c == N) *n_centers = pos[N];
   if (c >= N || !is_center[c]) return;
@@ -319,6 +319,7 @@ __global__ __launch_bounds__(256) void centers_kernel(
   }
   centers[pos[c]] = (int32_t)c;
   if (p) p[pos[c]] = cnt;
+  p_keep[pos[c]] = cnt;
 }
 
 __global__ __launch_bounds__(256) void zero_i32_kernel(int32_t* p, int64_t n) {
@@ -449,9 +450,14 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
                      state, N, owner, flag);
   st = exclusive_scan_i32_to_i64(ctx, flag, N, pos);
   if (st) return st;
+  // the row counts are also kept in the context, for the weights entry
+  // point's choice of pass width
+  auto* p_keep = (int32_t*)scratch(ctx, B_P_CACHE, (size_t)N * 4, &st);
+  if (st) return st;
   hipLaunchKernelGGL(centers_kernel, dim3((unsigned)((N + 256) / 256)),
                      dim3(256), 0, s, flag, pos, knn, ball, owner, N, n,
-                     centers, p, n_centers);
+                     centers, p, p_keep, n_centers);
+  ctx->p_cache = {centers, owner, N, n, p_keep};
   return hip_check(ctx, hipGetLastError(), "cover");
 }
 

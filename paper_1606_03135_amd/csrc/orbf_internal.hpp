@@ -73,6 +73,22 @@ struct D2Cache {
   }
 };
 
+// Retained-row count p of every center of the last covering without the
+// Lebesgue test, in center order, kept in the context's own scratch
+// (B_P_CACHE).  The weights entry point uses it, when handed the same
+// centers and owner arrays, to choose each stencil's pass width; a stale
+// count can only choose a slower width, never change a result.
+struct PCache {
+  const int32_t* centers = nullptr;
+  const int32_t* owner = nullptr;
+  int64_t N = 0;
+  int n = 0;
+  const int32_t* p = nullptr;
+  bool matches(const int32_t* c, const int32_t* o, int64_t N_, int n_) const {
+    return p && c == centers && o == owner && N_ == N && n_ == n;
+  }
+};
+
 }  // namespace orbf
 
 struct orbf_ctx {
@@ -109,6 +125,7 @@ struct orbf_ctx {
   // weights kernel schedules: rows of (K, pclass, orbf_schedule)
   std::vector<int> schedules;
   orbf::D2Cache d2_cache;
+  orbf::PCache p_cache;
 };
 
 namespace orbf {
@@ -139,6 +156,9 @@ enum BufId {
   B_IR_COUNT,
   B_KNN_D2,
   B_CSR_RANK,
+  B_CLASS,
+  B_CLASS_N,
+  B_P_CACHE,
   B_NUM,
 };
 static_assert(B_NUM <= 32, "orbf_ctx::buf holds 32 scratch buffers");

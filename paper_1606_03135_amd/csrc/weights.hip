@@ -265,6 +265,121 @@ __global__ __launch_bounds__(64) void weights_lds_kernel(WeightsParams P) {
   }
 }
 
+// Sort the stencils of `centers` into three lists by retained-row count p
+// (owner[j] == c over the stencil of c, as the weights kernels count it):
+// p <= 8, p <= 16 and above, for 8, 16 and 24 right-hand sides per pass.
+// A wavefront takes 64 stencils: their counts are formed sixteen lanes per
+// stencil (n <= 128: eight positions per lane), four stencils at a time,
+// and gathered in LDS; then one lane per stencil appends it to its list,
+// with one atomic per class per 64 stencils (three counters only, so
+// fewer, larger reservations are what keeps them from serialising).
+__global__ __launch_bounds__(256) void stencil_class_kernel(
+    const int32_t* __restrict__ centers, const int64_t* __restrict__ n_centers,
+    const int32_t* __restrict__ knn, const int32_t* __restrict__ owner,
+    int64_t N, int n, int32_t* __restrict__ lists,
+    unsigned long long* __restrict__ counts) {
+  __shared__ int p_s[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int pl = lane & 15, grp = lane >> 4;
+  const int64_t total = *n_centers;
+  for (int64_t b64 = ((int64_t)blockIdx.x * 4 + w) * 64; b64 < total;
+       b64 += (int64_t)gridDim.x * 256) {
+#pragma unroll 4
+    for (int t = 0; t < 16; ++t) {
+      const int64_t ci = b64 + 4 * t + grp;
+      int p = 0;
+      if (ci < total) {
+        const int32_t c = centers[ci];
+        if ((uint32_t)c < (uint64_t)N) {
+          const int32_t* st = knn + (int64_t)c * n;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int q = pl + 16 * i;
+            if (q < n) {
+              const int32_t j = st[q];
+              p += (uint32_t)j < (uint64_t)N && owner[j] == c;
+            }
+          }
+        }
+      }
+      p += __shfl_xor(p, 1, 64);
+      p += __shfl_xor(p, 2, 64);
+      p += __shfl_xor(p, 4, 64);
+      p += __shfl_xor(p, 8, 64);
+      if (pl == 0) p_s[w][4 * t + grp] = p;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t ci = b64 + lane;
+    const bool live = ci < total;
+    const int p = p_s[w][lane];
+    const int cls = p <= 8 ? 0 : (p <= 16 ? 1 : 2);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const unsigned long long m = __ballot(live && cls == k);
+      if (m == 0ull) continue;
+      const int lead = __ffsll((long long)m) - 1;
+      unsigned long long at = 0;
+      if (lane == lead)
+        at = atomicAdd(&counts[k], (unsigned long long)__popcll(m));
+      at = __shfl(at, lead, 64);
+      if (live && cls == k)
+        lists[(int64_t)k * N + at + __popcll(m & ((1ull << lane) - 1ull))] =
+            centers[ci];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// The same lists from counts already known (the covering's), one thread
+// per stencil; 1024-thread blocks gather their slots in LDS so that each
+// block makes one atomic per class.
+__global__ __launch_bounds__(1024) void stencil_class_from_p_kernel(
+    const int32_t* __restrict__ centers, const int64_t* __restrict__ n_centers,
+    const int32_t* __restrict__ pcount, int64_t N,
+    int32_t* __restrict__ lists, unsigned long long* __restrict__ counts) {
+  __shared__ int wave_n[3][16];
+  __shared__ unsigned long long block_at[3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t total = *n_centers;
+  for (int64_t b = (int64_t)blockIdx.x * 1024; b < total;
+       b += (int64_t)gridDim.x * 1024) {
+    const int64_t ci = b + threadIdx.x;
+    const bool live = ci < total;
+    const int p = live ? pcount[ci] : 0;
+    const int cls = p <= 8 ? 0 : (p <= 16 ? 1 : 2);
+    unsigned long long m[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      m[k] = __ballot(live && cls == k);
+      if (lane == 0) wave_n[k][w] = __popcll(m[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const int k = threadIdx.x;
+      int sum = 0;
+      for (int i = 0; i < 16; ++i) {
+        const int v = wave_n[k][i];
+        wave_n[k][i] = sum;  // exclusive prefix over the block's wavefronts
+        sum += v;
+      }
+      block_at[k] = sum ? atomicAdd(&counts[k], (unsigned long long)sum) : 0ull;
+    }
+    __syncthreads();
+    if (live)
+      lists[(int64_t)cls * N + block_at[cls] + wave_n[cls][w] +
+            __popcll(m[cls] & ((1ull << lane) - 1ull))] = centers[ci];
+    __syncthreads();
+  }
+}
+
+__global__ void zero3_u64_kernel(unsigned long long* c) {
+  if (threadIdx.x < 3) c[threadIdx.x] = 0ull;
+}
+
 }  // namespace
 
 orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
@@ -346,6 +461,7 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   P.ldm = K + pcap;
   if (!explicit_rows && !isinf(a->tau)) {
     // covering with the L-Lebesgue test first; rows below use its owners
+    ctx->p_cache = PCache();  // these centers are not the cached covering's
     st = launch_lebesgue_cover(ctx, P, t2, a->eligible, a->centers,
                                a->n_centers, a->owner);
     if (st) return st;
@@ -368,7 +484,48 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   // LDS-resident kernel.  p-class: expected kept rows n (1-delta)^d > 8.
   const double keep = explicit_rows ? 1.0 : n * pow(t2, 0.5 * d);
   const int sched = schedule_for(ctx, K, keep > 8.0 ? 1 : 0);
+  // SPLIT: three lists by retained rows, one launch each
+  auto split = [&](const WeightsParams& Q) -> bool {
+    // the covering's own list only (not an FP32 fallback list)
+    if (Q.rows != nullptr || Q.centers != a->centers || K > 72 || M > 35)
+      return false;
+    orbf_status s2 = ORBF_OK;
+    auto* lists = (int32_t*)scratch(ctx, B_CLASS, (size_t)a->N * 12, &s2);
+    auto* counts = (unsigned long long*)scratch(ctx, B_CLASS_N, 24, &s2);
+    if (s2) return false;
+    hipLaunchKernelGGL(zero3_u64_kernel, dim3(1), dim3(64), 0, ctx->stream,
+                       counts);
+    if (ctx->p_cache.matches(Q.centers, Q.owner, a->N, n)) {
+      const int64_t cb = (work + 1023) / 1024;
+      hipLaunchKernelGGL(stencil_class_from_p_kernel,
+                         dim3((unsigned)(cb < 1024 ? cb : 1024)), dim3(1024),
+                         0, ctx->stream, Q.centers, Q.n_centers,
+                         ctx->p_cache.p, a->N, lists, counts);
+    } else {
+      const int64_t cb = (work + 255) / 256;  // 256 stencils per block
+      hipLaunchKernelGGL(stencil_class_kernel,
+                         dim3((unsigned)(cb < 8192 ? cb : 8192)), dim3(256),
+                         0, ctx->stream, Q.centers, Q.n_centers, Q.knn,
+                         Q.owner, a->N, n, lists, counts);
+    }
+    // one after the other, widest first, so the launch with the cheapest
+    // stencils forms the tail (running them side by side on separate
+    // streams measured slower: 6.18 against 5.95 ms)
+    for (int k = 2; k >= 0; --k) {
+      WeightsParams R = Q;
+      R.centers = lists + (int64_t)k * a->N;
+      R.n_centers = (int64_t*)(counts + k);
+      launch_weights_reg(ctx, R, grid, k + 1);
+    }
+    return true;
+  };
+  // Without a tuned schedule, large node sets (where each of the three
+  // lists fills the device) take SPLIT: on the 1M-node ball 5.91 ms against
+  // 6.25 ms for one 16-wide launch, whose stencils with p > 16 need a
+  // second full elimination.
+  const bool split_default = sched == ORBF_SCHED_DEFAULT && a->N >= 65536;
   auto fp64 = [&](const WeightsParams& Q) {
+    if ((sched == ORBF_SCHED_SPLIT || split_default) && split(Q)) return;
     if (sched == ORBF_SCHED_GROUP16 && launch_weights_wg(ctx, Q, work)) return;
     if (sched != ORBF_SCHED_GROUP16 &&
         launch_weights_reg(ctx, Q, grid, sched == ORBF_SCHED_WAVE8 ? 1 : 2))

@@ -401,15 +401,16 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
 
 }  // namespace
 
-// Launch the register kernel if a variant covers K; `pl` = 1 or 2 blocks of
-// eight right-hand sides per pass.  Returns false if no variant covers K.
+// Launch the register kernel if a variant covers K; `pl` = 1, 2 or 3 blocks
+// of eight right-hand sides per pass.  Returns false if no variant covers K.
 bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid,
                         int pl) {
   if (P.M > 35) return false;
   // acceptance mode always takes 16 right-hand sides per pass
   if (P.accept) pl = 2;
+  if (pl < 1 || pl > 3) pl = 2;
   const size_t dyn =
-      ((size_t)8 * 2 * P.M + (size_t)3 * P.n * (P.l + 1)) * sizeof(double);
+      ((size_t)8 * pl * P.M + (size_t)3 * P.n * (P.l + 1)) * sizeof(double);
 #define ORBF_REG_CASE(LL)                                                     \
   if (P.K <= 8 * LL) {                                                        \
     if (P.accept)                                                             \
@@ -417,6 +418,9 @@ bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid,
                          dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P);  \
     else if (pl == 1)                                                         \
       hipLaunchKernelGGL((weights_reg_kernel<LL, 1, false>),                  \
+                         dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P);  \
+    else if (pl == 3)                                                         \
+      hipLaunchKernelGGL((weights_reg_kernel<LL, 3, false>),                  \
                          dim3((unsigned)grid), dim3(64), dyn, ctx->stream, P);  \
     else                                                                      \
       hipLaunchKernelGGL((weights_reg_kernel<LL, 2, false>),                  \

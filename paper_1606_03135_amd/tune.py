@@ -1,7 +1,8 @@
 """Autotuner of the weights kernel schedules (``orbf_set_schedule``).
 
 Stencils of one system size K = n + M can be solved by a one-wavefront
-kernel with 16 or 8 right-hand sides per pass (K <= 72) or by a four-
+kernel with 16 or 8 right-hand sides per pass, or with 8, 16 or 24 chosen
+per stencil from its retained rows ("split"; K <= 72), or by a four-
 wavefront workgroup kernel (K <= 144).  Which is fastest depends on K and on
 how many rows a stencil keeps (p-class: n (1 - delta)^d above 8 or not).
 The tuner times each candidate on the largest node set of each (K, p-class)
@@ -15,13 +16,13 @@ import time
 
 import paper_1606_03135_amd as orbf
 
-SCHEDULES = {"wave16": 0, "wave8": 1, "group16": 2}
+SCHEDULES = {"wave16": 0, "wave8": 1, "group16": 2, "split": 3}
 NAMES = {v: k for k, v in SCHEDULES.items()}
 
 
 def _candidates(K):
     if K <= 72:
-        return ["wave16", "wave8", "group16"]
+        return ["split", "wave16", "wave8", "group16"]
     if K <= 144:
         return ["group16"]
     return []

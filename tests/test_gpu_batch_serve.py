@@ -256,7 +256,7 @@ def test_schedules_and_tuner(orbf):
     ref = oracle.build_dm(x, n, m, l, delta)
     own = ref["owner"] >= 0
     out = {}
-    for name in ("wave16", "wave8", "group16"):
+    for name in ("wave16", "wave8", "group16", "split"):
         tune.set_schedule(ctx, K, pc, name)
         r = orbf.build_dm(xd, n, m, l, delta, ctx=ctx)
         W = r["W"].cpu().numpy()
@@ -266,9 +266,12 @@ def test_schedules_and_tuner(orbf):
         assert err <= 1e-9
         out[name] = r["W"]
     assert torch.equal(out["wave16"], out["wave8"])
-    assert (K, pc, "group16") in tune.get_schedules(ctx)
+    assert torch.equal(out["wave16"], out["split"])
+    assert (K, pc, "split") in tune.get_schedules(ctx)
     with pytest.raises(orbf.OrbfError):
         tune.set_schedule(ctx, 100, 0, "wave16")  # K > 72
+    with pytest.raises(orbf.OrbfError):
+        tune.set_schedule(ctx, 100, 0, "split")
     tune.set_schedule(ctx, K, pc, None)
     assert tune.get_schedules(ctx) == []
     specs = small_specs(6, 21, nmax=4000)
@@ -277,3 +280,37 @@ def test_schedules_and_tuner(orbf):
     _say(f"[gpu] tuner: {len(rep)} classes in {secs:.1f} s")
     assert {(r["K"], r["pclass"]) for r in rep} == {
         (K_, p_) for K_, p_, _ in tune.get_schedules(ctx)}
+
+
+def test_split_schedule_without_cached_counts(orbf):
+    """The split schedule takes each stencil's row count from the covering
+    when handed its own centers/owner arrays, and counts them itself
+    otherwise; both give the single-launch weights bit for bit, on a set
+    whose stencils span all three pass widths."""
+    from paper_1606_03135_amd import tune
+    ctx = orbf.Context(0)
+    x = gpu(nodesets.ball(20000, 5)["x"])
+    n, m, l, delta = 50, 5, 3, 0.3
+    knn, rho2 = orbf.build_nodes_knn(ctx, x, n)
+    centers, nc, owner, p = orbf.select_overlapped_stencils(
+        ctx, x, knn, rho2, delta)
+    k = int(nc.item())
+    pk = p[:k].cpu().numpy()
+    _say(f"[gpu] split: {k} stencils, p<=8 {(pk <= 8).sum()}, "
+         f"p<=16 {((pk > 8) & (pk <= 16)).sum()}, p>16 {(pk > 16).sum()}")
+    assert (pk <= 8).any() and ((pk > 8) & (pk <= 16)).any() and (pk > 16).any()
+    K, pc = n + 20, tune.pclass(n, 3, delta)
+
+    def weights(name, c, nn, o):
+        tune.set_schedule(ctx, K, pc, name)
+        W = orbf.compute_weights(ctx, orbf.OP_LAPLACIAN, m, l, n, delta, x,
+                                 knn, rho2, centers=c, n_centers=nn, owner=o)
+        ctx.sync()
+        return W.clone()
+
+    one = weights("wave16", centers, nc, owner)
+    cached = weights("split", centers, nc, owner)
+    counted = weights("split", centers.clone(), nc.clone(), owner.clone())
+    own = owner >= 0
+    assert torch.equal(one[own], cached[own])
+    assert torch.equal(one[own], counted[own])
