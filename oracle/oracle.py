@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborbf_oracle.so")
 
 OK, EINVAL, EDUPLICATE, ESINGULAR = 0, 1, 2, 3
-OP_LAPLACIAN, OP_NEUMANN = 0, 1
+OP_LAPLACIAN, OP_NEUMANN, OP_DX, OP_DY, OP_DZ, OP_IDENTITY = 0, 1, 2, 3, 4, 5
 _NAMES = {EINVAL: "EINVAL", EDUPLICATE: "EDUPLICATE", ESINGULAR: "ESINGULAR"}
 
 
@@ -60,6 +60,9 @@ def _declare(L):
     L.orc_overlapped_rows.argtypes = [_P, _I64, _I, _I, _I, _I, _P, _P, _D,
                                       _D, _P, _P, _P, _P, _P, _P, _P, _I]
     L.orc_overlapped_rows.restype = _I
+    L.orc_overlapped_rows_op.argtypes = [_P, _I64, _I, _I, _I, _I, _I, _P,
+                                         _P, _D, _P, _P, _P, _P, _P, _P, _I]
+    L.orc_overlapped_rows_op.restype = _I
     L.orc_center_rows.argtypes = [_P, _I64, _I, _I, _I, _I, _I, _P, _I64, _P,
                                   _P, _P, _P, _I]
     L.orc_center_rows.restype = _I
@@ -188,6 +191,33 @@ def overlapped_rows(x, knn_idx, rho2, m, l, delta, tau=np.inf, eligible=None,
                 min_margin=mm.value)
 
 
+def overlapped_rows_op(x, knn_idx, rho2, m, l, delta, op, eligible=None,
+                       nthreads=0):
+    """DM rows of operator op (LAPLACIAN, DX, DY, DZ or IDENTITY) on the
+    greedy covering without the Lebesgue test (Sec. 4.1: the right-hand
+    sides are L applied to the basis; weights divided by rho^theta).
+
+    Returns dict(owner, centers, W[N,n], lam[N])."""
+    x = _f64(x)
+    N, d = x.shape
+    n = knn_idx.shape[1]
+    knn_idx = _i32(knn_idx)
+    rho2 = _f64(rho2)
+    el = None if eligible is None else np.ascontiguousarray(eligible, np.uint8)
+    owner = np.empty(N, np.int32)
+    centers = np.empty(N, np.int32)
+    nc = ctypes.c_int64()
+    W = np.zeros((N, n), np.float64)
+    lam = np.zeros(N, np.float64)
+    _check(lib().orc_overlapped_rows_op(_ptr(x), N, d, n, m, l, int(op),
+                                        _ptr(knn_idx), _ptr(rho2),
+                                        float(delta), _ptr(el), _ptr(owner),
+                                        _ptr(centers), ctypes.byref(nc),
+                                        _ptr(W), _ptr(lam), int(nthreads)),
+           "overlapped_rows_op")
+    return dict(owner=owner, centers=centers[: nc.value].copy(), W=W, lam=lam)
+
+
 def center_rows(x, knn_idx, m, l, rows, op=OP_LAPLACIAN, normals=None,
                 owner=None, W=None, nthreads=0):
     """delta = 1 rows of the listed nodes, each on its own stencil (boundary
@@ -224,12 +254,20 @@ def csr(knn_idx, owner, W):
 
 
 def build_dm(x, n, m, l, delta, tau=np.inf, eligible=None, boundary=None,
-             normals=None, nthreads=0, knn_method="auto"):
-    """Whole oracle pipeline: stencils, covering (+Lebesgue), interior
-    Laplacian rows, optional normal-derivative rows at ``boundary`` nodes,
-    CSR.  Returns a dict with every intermediate."""
+             normals=None, nthreads=0, knn_method="auto", op=OP_LAPLACIAN):
+    """Whole oracle pipeline: stencils, covering (+Lebesgue), interior rows
+    of operator ``op`` (the Lebesgue test only with the Laplacian), optional
+    normal-derivative rows at ``boundary`` nodes, CSR.  Returns a dict with
+    every intermediate."""
     idx, rho2 = knn(x, n, knn_method)
-    r = overlapped_rows(x, idx, rho2, m, l, delta, tau, eligible, nthreads)
+    if op == OP_LAPLACIAN:
+        r = overlapped_rows(x, idx, rho2, m, l, delta, tau, eligible,
+                            nthreads)
+    else:
+        if not np.isinf(tau):
+            raise ValueError("the Lebesgue test is defined for the Laplacian")
+        r = overlapped_rows_op(x, idx, rho2, m, l, delta, op, eligible,
+                               nthreads)
     owner, W = r["owner"], r["W"]
     if boundary is not None and len(boundary):
         center_rows(x, idx, m, l, boundary, OP_NEUMANN, normals, owner, W,

@@ -413,8 +413,9 @@ int orc_stencil_weights(int d, int m, int l, int op, int n, const double* P,
                         double* W) {
   if ((d != 2 && d != 3) || m < 3 || (m % 2) == 0 || l < 0 || ne < 1)
     return ORC_EINVAL;
-  if (op != ORC_OP_LAPLACIAN && op != ORC_OP_NEUMANN) return ORC_EINVAL;
+  if (op < ORC_OP_LAPLACIAN || op > ORC_OP_IDENTITY) return ORC_EINVAL;
   if (op == ORC_OP_NEUMANN && nrm == NULL) return ORC_EINVAL;
+  if (op == ORC_OP_DZ && d != 3) return ORC_EINVAL;
   int M = orc_num_monomials(d, l);
   if (n < M || n < 1) return ORC_EINVAL;
   int K = n + M;
@@ -449,34 +450,46 @@ int orc_stencil_weights(int d, int m, int l, int op, int n, const double* P,
       A[(n + t) * K + i] = v;
     }
   }
-  /* B_hat: column e is L applied to each basis function at point e */
+  /* B_hat: column e is L applied to each basis function at point e; a
+   * first derivative d/dx_a is the directional derivative along e_a */
   for (int e = 0; e < ne; e++) {
     const double* pe = ev + e * 3;
+    double dir[3] = {0.0, 0.0, 0.0};
+    if (op == ORC_OP_NEUMANN)
+      for (int a = 0; a < d; a++) dir[a] = nrm[e * d + a];
+    else if (op >= ORC_OP_DX && op <= ORC_OP_DZ)
+      dir[op - ORC_OP_DX] = 1.0;
     for (int j = 0; j < n; j++) {
       double r2 = sqdist(pe, xi + j * 3, d);
       double v;
       if (op == ORC_OP_LAPLACIAN) {
         /* Laplacian of r^m in d dimensions: m (m + d - 2) r^(m-2) */
         v = (double)(m * (m + d - 2)) * odd_power(r2, m - 2);
+      } else if (op == ORC_OP_IDENTITY) {
+        v = odd_power(r2, m);
       } else {
         /* gradient of r^m is m r^(m-2) (x - x_j) */
         double dot = 0.0;
         for (int a = 0; a < d; a++)
-          dot = dot + (pe[a] - xi[j * 3 + a]) * nrm[e * d + a];
+          dot = dot + (pe[a] - xi[j * 3 + a]) * dir[a];
         v = ((double)m * odd_power(r2, m - 2)) * dot;
       }
       B[j * ne + e] = v;
     }
     for (int t = 0; t < M; t++)
-      B[(n + t) * ne + e] = (op == ORC_OP_LAPLACIAN)
-                                ? monomial_lap(pe, ex + 3 * t, d)
-                                : monomial_dn(pe, ex + 3 * t, nrm + e * d, d);
+      B[(n + t) * ne + e] =
+          (op == ORC_OP_LAPLACIAN)   ? monomial_lap(pe, ex + 3 * t, d)
+          : (op == ORC_OP_IDENTITY) ? monomial(pe, ex + 3 * t, d)
+                                    : monomial_dn(pe, ex + 3 * t, dir, d);
   }
 
   int st = ge_solve(K, ne, A, B);
   if (st == ORC_OK) {
-    /* undo the 1/rho scaling: theta = 2 (Laplacian) or 1 (normal deriv.) */
-    double sc = (op == ORC_OP_LAPLACIAN) ? rho2 : rho;
+    /* undo the 1/rho scaling: theta = 2 (Laplacian), 1 (first derivatives)
+     * or 0 (identity) */
+    double sc = (op == ORC_OP_LAPLACIAN) ? rho2
+                : (op == ORC_OP_IDENTITY) ? 1.0
+                                          : rho;
     for (int e = 0; e < ne; e++)
       for (int j = 0; j < n; j++) W[e * n + j] = B[j * ne + e] / sc;
   }
@@ -533,22 +546,16 @@ static int stencil_cols(const double* x, int d, int n, int m, int l, int op,
   return orc_stencil_weights(d, m, l, op, n, P, ne, E, nrm, W);
 }
 
-int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
-                        const int32_t* knn, const double* rho2, double delta,
-                        double tau, const uint8_t* eligible, int32_t* owner,
+/* covering first, then every center's columns independently */
+static int covered_rows(const double* x, int64_t N, int d, int n, int m,
+                        int l, int op, const int32_t* knn, const double* rho2,
+                        double delta, const uint8_t* eligible, int32_t* owner,
                         int32_t* centers, int64_t* n_centers, double* Wrows,
-                        double* lam, double* min_margin, int nthreads) {
-  if ((d != 2 && d != 3) || n < 1 || n > N || !(delta >= 0.0 && delta <= 1.0))
-    return ORC_EINVAL;
-  if (!(tau >= 1.0)) return ORC_EINVAL; /* tau = +inf disables the test */
-  if (n < orc_num_monomials(d, l) || m < 3 || m % 2 == 0) return ORC_EINVAL;
-  int err = ORC_OK;
-  double margin = INFINITY;
-  if (isinf(tau)) {
-    /* covering first, then every center's columns independently */
-    err = orc_cover(x, N, d, n, knn, rho2, delta, eligible, owner, centers,
-                    n_centers);
-    if (err) return err;
+                        double* lam, int nthreads) {
+  int err = orc_cover(x, N, d, n, knn, rho2, delta, eligible, owner, centers,
+                      n_centers);
+  if (err) return err;
+  {
     int64_t nc = *n_centers;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -566,8 +573,7 @@ int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
         int ne = 0;
         for (int q = 0; q < n; q++)
           if (owner[st[q]] == k) qs[ne++] = q;
-        int r = stencil_cols(x, d, n, m, l, ORC_OP_LAPLACIAN, st, ne, qs, NULL,
-                             P, E, W);
+        int r = stencil_cols(x, d, n, m, l, op, st, ne, qs, NULL, P, E, W);
         if (r != ORC_OK) {
 #pragma omp critical
           err = r;
@@ -584,6 +590,42 @@ int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
       free(E);
       free(W);
     }
+  }
+  return err;
+}
+
+int orc_overlapped_rows_op(const double* x, int64_t N, int d, int n, int m,
+                           int l, int op, const int32_t* knn,
+                           const double* rho2, double delta,
+                           const uint8_t* eligible, int32_t* owner,
+                           int32_t* centers, int64_t* n_centers,
+                           double* Wrows, double* lam, int nthreads) {
+  if ((d != 2 && d != 3) || n < 1 || n > N || !(delta >= 0.0 && delta <= 1.0))
+    return ORC_EINVAL;
+  if (n < orc_num_monomials(d, l) || m < 3 || m % 2 == 0) return ORC_EINVAL;
+  if (op != ORC_OP_LAPLACIAN && op != ORC_OP_DX && op != ORC_OP_DY &&
+      op != ORC_OP_DZ && op != ORC_OP_IDENTITY)
+    return ORC_EINVAL;
+  if (op == ORC_OP_DZ && d != 3) return ORC_EINVAL;
+  return covered_rows(x, N, d, n, m, l, op, knn, rho2, delta, eligible, owner,
+                      centers, n_centers, Wrows, lam, nthreads);
+}
+
+int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
+                        const int32_t* knn, const double* rho2, double delta,
+                        double tau, const uint8_t* eligible, int32_t* owner,
+                        int32_t* centers, int64_t* n_centers, double* Wrows,
+                        double* lam, double* min_margin, int nthreads) {
+  if ((d != 2 && d != 3) || n < 1 || n > N || !(delta >= 0.0 && delta <= 1.0))
+    return ORC_EINVAL;
+  if (!(tau >= 1.0)) return ORC_EINVAL; /* tau = +inf disables the test */
+  if (n < orc_num_monomials(d, l) || m < 3 || m % 2 == 0) return ORC_EINVAL;
+  int err = ORC_OK;
+  double margin = INFINITY;
+  if (isinf(tau)) {
+    err = covered_rows(x, N, d, n, m, l, ORC_OP_LAPLACIAN, knn, rho2, delta,
+                       eligible, owner, centers, n_centers, Wrows, lam,
+                       nthreads);
     if (min_margin) *min_margin = margin;
     return err;
   }

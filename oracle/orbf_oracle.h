@@ -35,7 +35,19 @@ enum {
   ORC_ESINGULAR = 3   /* exact zero pivot in a local saddle system     */
 };
 
-enum { ORC_OP_LAPLACIAN = 0, ORC_OP_NEUMANN = 1 };
+/* Operators L (Sec. 4.1: the right-hand sides are L applied to the RBF and
+ * polynomial basis at the evaluation points; the scaled solve is divided by
+ * rho^theta, theta the order of L).  NEUMANN: n . grad with a given unit
+ * normal per point (theta 1); DX, DY, DZ: d/dx_a (theta 1); IDENTITY: the
+ * value itself (interpolation, theta 0). */
+enum {
+  ORC_OP_LAPLACIAN = 0,
+  ORC_OP_NEUMANN = 1,
+  ORC_OP_DX = 2,
+  ORC_OP_DY = 3,
+  ORC_OP_DZ = 4,
+  ORC_OP_IDENTITY = 5
+};
 
 /* Number of monomials of total degree <= l in d variables, C(l+d, d). */
 int orc_num_monomials(int d, int l);
@@ -94,6 +106,15 @@ int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
                         double tau, const uint8_t* eligible, int32_t* owner,
                         int32_t* centers, int64_t* n_centers, double* Wrows,
                         double* lam, double* min_margin, int nthreads);
+
+/* The same rows (infinite tau only) for another operator: LAPLACIAN, DX,
+ * DY, DZ (d = 3) or IDENTITY. */
+int orc_overlapped_rows_op(const double* x, int64_t N, int d, int n, int m,
+                           int l, int op, const int32_t* knn,
+                           const double* rho2, double delta,
+                           const uint8_t* eligible, int32_t* owner,
+                           int32_t* centers, int64_t* n_centers,
+                           double* Wrows, double* lam, int nthreads);
 
 /* Standard (delta = 1) rows for an explicit list of nodes with operator op
  * (boundary pass of Sec. 5: normal-derivative rows at boundary nodes, each
