@@ -75,7 +75,12 @@ def lu_flops(K, p):
     return (2.0 * K ** 3 / 3.0 - K ** 2 / 2.0 - K / 6.0) + p * (2.0 * K * K - K)
 
 
-def cpu_baseline(n, m, l, delta, n_sample):
+OPS = {"laplacian": ("OP_LAPLACIAN", "Laplacian"), "dx": ("OP_DX", "d/dx"),
+       "dy": ("OP_DY", "d/dy"), "dz": ("OP_DZ", "d/dz"),
+       "identity": ("OP_IDENTITY", "identity")}
+
+
+def cpu_baseline(n, m, l, delta, n_sample, op="laplacian"):
     import nodesets
     import oracle
     threads = min(16, len(os.sched_getaffinity(0)))
@@ -83,7 +88,7 @@ def cpu_baseline(n, m, l, delta, n_sample):
     os.environ.setdefault("OMP_NUM_THREADS", str(threads))
     t0 = time.perf_counter()
     r = oracle.build_dm(x, n, m, l, delta, nthreads=threads,
-                        knn_method="grid")
+                        knn_method="grid", op=getattr(oracle, OPS[op][0]))
     dt = time.perf_counter() - t0
     nnz = len(r["val"])
     return {"value": nnz / dt, "unit": "weights/s", "cores": threads,
@@ -114,10 +119,13 @@ def bench_ball(args, torch, orbf, nodesets):
     xd = torch.from_numpy(x).to(dev)
     ctx = orbf.Context(0)
 
+    op = getattr(orbf, OPS[args.op][0])
+    opname = OPS[args.op][1]
+
     def run(prec, steps, warmup):
         def step():
             return orbf.build_dm(xd, n, m, l, delta, ctx=ctx, sync=True,
-                                 prec=prec)
+                                 prec=prec, op=op)
         r = None
         for _ in range(max(warmup, 1)):
             r = step()
@@ -147,7 +155,7 @@ def bench_ball(args, torch, orbf, nodesets):
     knn_bytes = N * 3 * 8 + N * n * 4 + N * 8
     csr_bytes = nnz * 12 + (N + 1) * 8
     out = {
-        "metric": "RBF-FD weights/sec building 3D Laplacian DM (N=1M); "
+        "metric": f"RBF-FD weights/sec building 3D {opname} DM (N=1M); "
                   "p50/p99 request latency",
         "value": value,
         "unit": "weights/s",
@@ -162,7 +170,7 @@ def bench_ball(args, torch, orbf, nodesets):
         "data": "synthetic",
         "config": {"workload": f"3D unit ball N={N} (scrambled Halton + "
                                f"Fibonacci shell), PHS r^5, l=3 (M=20), "
-                               f"n=50, delta=0.3, Laplacian, FP64",
+                               f"n=50, delta=0.3, {opname}, FP64",
                    "N": N, "n": n, "m": m, "l": l, "delta": delta,
                    "parallelism": "single GPU"},
         "stencils_per_s": nc * args.steps / elapsed,
@@ -214,7 +222,8 @@ def bench_ball(args, torch, orbf, nodesets):
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = COPY_BYTES
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, m, l, delta, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(n, m, l, delta, args.cpu_sample,
+                                           args.op)
     return out
 
 
@@ -380,6 +389,9 @@ def main():
     ap.add_argument("--workload", default="ball",
                     choices=["ball", "batched", "serving"])
     ap.add_argument("--N", type=int, default=1_000_000)
+    ap.add_argument("--op", default="laplacian", choices=sorted(OPS),
+                    help="operator of the ball workload's DM (the headline "
+                         "is the Laplacian)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="nodes of the ball the oracle builds (default: the "
                          "whole workload)")

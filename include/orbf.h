@@ -55,10 +55,21 @@ typedef enum orbf_status {
   ORBF_EINTERNAL = 7   /* an internal limit was hit (message says which)      */
 } orbf_status;
 
+/* The operator L whose DM is built (Sec. 4.1: the right-hand sides are L
+ * applied to the RBF and polynomial basis at each computed row's node, and
+ * the weights are unscaled by rho^theta, theta the order of L). */
 typedef enum orbf_op {
-  ORBF_OP_LAPLACIAN = 0, /* L = Laplacian (interior rows, Sec. 4.1 / Sec. 7)  */
-  ORBF_OP_NEUMANN = 1    /* L = n . grad, the normal derivative of the
-                            Neumann boundary operator (Sec. 5)               */
+  ORBF_OP_LAPLACIAN = 0, /* L = Laplacian (interior rows, Sec. 4.1 / Sec. 7),
+                            theta = 2                                        */
+  ORBF_OP_NEUMANN = 1,   /* L = n . grad, the normal derivative of the
+                            Neumann boundary operator (Sec. 5), theta = 1;
+                            explicit rows with normals only                  */
+  ORBF_OP_DX = 2,        /* L = d/dx, theta = 1                              */
+  ORBF_OP_DY = 3,        /* L = d/dy, theta = 1                              */
+  ORBF_OP_DZ = 4,        /* L = d/dz (d = 3), theta = 1                      */
+  ORBF_OP_IDENTITY = 5   /* L = I (interpolation at the row's node),
+                            theta = 0: every row is the unit vector of its
+                            node, up to rounding                             */
 } orbf_op;
 
 typedef enum orbf_prec {
@@ -189,9 +200,11 @@ typedef struct orbf_weights_args {
  * (n+M) x (n+M) system [A Psi; Psi^T 0] with A_ij = |xi_i - xi_j|^m and Psi
  * the M = C(l+d, d) monomials of degree <= l, one right-hand side per
  * computed row e holding L|xi - xi_j|^m and L psi at xi_e; partial-pivot LU
- * and triangular solves; weights unscaled by rho_k^2 (Laplacian) or rho_k
- * (normal derivative); W^psi is discarded.
- *   op : ORBF_OP_LAPLACIAN (needs m >= 3) or ORBF_OP_NEUMANN (mode (a) only)
+ * and triangular solves; weights unscaled by rho_k^theta (2 for the
+ * Laplacian, 1 for first derivatives, 0 for the identity); W^psi is
+ * discarded.
+ *   op : LAPLACIAN, DX, DY, DZ or IDENTITY in modes (a) and (b); NEUMANN in
+ *        mode (a) only; mode (c), the Lebesgue test, with the LAPLACIAN
  *   m  : odd PHS exponent >= 3;  l : polynomial degree >= 0;
  *   n  : stencil size (>= M);    delta : overlap parameter in [0,1] (mode c)
  * Errors: EINVAL (parameters, NULL outputs, n + M > 160, mode/op mismatch),

@@ -30,7 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborbf.so")
 
 OK, EINVAL, EDUPLICATE, ESINGULAR, ENOMEM, EBUDGET, EHIP, EINTERNAL = range(8)
-OP_LAPLACIAN, OP_NEUMANN = 0, 1
+OP_LAPLACIAN, OP_NEUMANN, OP_DX, OP_DY, OP_DZ, OP_IDENTITY = 0, 1, 2, 3, 4, 5
 PREC_FP64, PREC_FP32_IR = 0, 1
 STATUS_NAMES = ["OK", "EINVAL", "EDUPLICATE", "ESINGULAR", "ENOMEM",
                 "EBUDGET", "EHIP", "EINTERNAL"]
@@ -300,10 +300,12 @@ def assemble_csr(ctx, knn, owner, W):
 
 def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
              boundary=None, normals=None, prec=PREC_FP64, ctx=None,
-             sync=True):
-    """Whole DM build on the device: stencils, covering, interior Laplacian
-    rows, optional normal-derivative rows at ``boundary`` nodes, CSR.
-    Returns a dict of device tensors (plus ``ctx``)."""
+             sync=True, op=OP_LAPLACIAN):
+    """Whole DM build on the device: stencils, covering, interior rows of
+    operator ``op`` (LAPLACIAN, DX, DY, DZ or IDENTITY; a finite ``tau``
+    only with the Laplacian), optional normal-derivative rows at
+    ``boundary`` nodes, CSR.  Returns a dict of device tensors (plus
+    ``ctx``)."""
     own_ctx = ctx is None
     if own_ctx:
         ctx = Context(xyz.device.index or 0)
@@ -323,7 +325,7 @@ def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
     if prec == PREC_FP32_IR:
         ir_steps = torch.empty(xyz.shape[0], dtype=torch.int32,
                                device=xyz.device)
-    W = compute_weights(ctx, OP_LAPLACIAN, m, l, n, delta, xyz, knn, rho2,
+    W = compute_weights(ctx, op, m, l, n, delta, xyz, knn, rho2,
                         centers=centers, n_centers=n_centers, owner=owner,
                         eligible=eligible, tau=tau, prec=prec, lebesgue=lam,
                         ir_steps=ir_steps)

@@ -276,8 +276,10 @@ orbf_status orbf_compute_weights(orbf_ctx* ctx, orbf_op op, int m, int l,
   if (!ctx || !a) return ORBF_EINVAL;
   orbf_status st = check_common(ctx, a->N, a->d, n);
   if (st) return st;
-  if (op != ORBF_OP_LAPLACIAN && op != ORBF_OP_NEUMANN)
+  if (op < ORBF_OP_LAPLACIAN || op > ORBF_OP_IDENTITY)
     return fail(ctx, ORBF_EINVAL, "unknown operator");
+  if (op == ORBF_OP_DZ && a->d != 3)
+    return fail(ctx, ORBF_EINVAL, "d/dz needs d = 3");
   if (m < 3 || m % 2 == 0)
     return fail(ctx, ORBF_EINVAL, "PHS exponent m must be odd and >= 3");
   if (l < 0) return fail(ctx, ORBF_EINVAL, "polynomial degree l < 0");
@@ -297,9 +299,12 @@ orbf_status orbf_compute_weights(orbf_ctx* ctx, orbf_op op, int m, int l,
     if (op == ORBF_OP_NEUMANN && !a->normals)
       return fail(ctx, ORBF_EINVAL, "NEUMANN rows need normals");
   } else {
-    if (op != ORBF_OP_LAPLACIAN)
+    if (op == ORBF_OP_NEUMANN)
       return fail(ctx, ORBF_EINVAL,
-                  "covered rows use the Laplacian; list boundary rows explicitly");
+                  "normal-derivative rows need normals: list them explicitly");
+    if (op != ORBF_OP_LAPLACIAN && !isinf(a->tau))
+      return fail(ctx, ORBF_EINVAL,
+                  "the Lebesgue test (finite tau) is for the Laplacian");
     if (!a->centers || !a->n_centers || !a->owner)
       return fail(ctx, ORBF_EINVAL, "NULL covering pointer");
   }

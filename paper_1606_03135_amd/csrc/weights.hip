@@ -48,9 +48,11 @@ __device__ __forceinline__ double mono(const double* p, const int8_t* e,
   return r;
 }
 
-// L psi at p: Laplacian sum_a e_a(e_a-1) p^(e-2eps_a) or n . grad
+// L psi at p: Laplacian sum_a e_a(e_a-1) p^(e-2eps_a), identity p^e, or a
+// first derivative along nrm (a normal, or e_a for d/dx_a)
 __device__ double mono_op(const double* p, const int8_t* e, int d, int op,
                           const double* nrm) {
+  if (op == ORBF_OP_IDENTITY) return mono(p, e, d);
   double s = 0.0;
   for (int a = 0; a < d; ++a) {
     int f[3] = {e[0], e[1], d == 3 ? e[2] : 0};
@@ -82,6 +84,7 @@ __device__ __forceinline__ double phs_op(const double* p, const double* q,
   const double r2 = dx * dx + dy * dy + dz * dz;
   if (op == ORBF_OP_LAPLACIAN)  // Laplacian of r^m: m (m + d - 2) r^(m-2)
     return (double)(m * (m + d - 2)) * odd_pow(r2, m - 2);
+  if (op == ORBF_OP_IDENTITY) return odd_pow(r2, m);
   // gradient of r^m: m r^(m-2) (x - x_j)
   double dot = dx * nrm[0] + dy * nrm[1];
   if (d == 3) dot += dz * nrm[2];
@@ -113,6 +116,9 @@ __global__ __launch_bounds__(64) void weights_lds_kernel(WeightsParams P) {
     double nv[3] = {0, 0, 0};
     if (explicit_rows && P.op == ORBF_OP_NEUMANN) {
       for (int a = 0; a < d; ++a) nv[a] = P.normals[ci * d + a];
+      nrm = nv;
+    } else if (P.op >= ORBF_OP_DX && P.op <= ORBF_OP_DZ) {
+      nv[P.op - ORBF_OP_DX] = 1.0;
       nrm = nv;
     }
     bool bad = false;
@@ -165,7 +171,9 @@ __global__ __launch_bounds__(64) void weights_lds_kernel(WeightsParams P) {
     }
     wave_sync();
     bool singular = false;
-    const double scale = (P.op == ORBF_OP_LAPLACIAN) ? r2c : rho;
+    const double scale = (P.op == ORBF_OP_LAPLACIAN) ? r2c
+                         : (P.op == ORBF_OP_IDENTITY) ? 1.0
+                                                      : rho;
     for (int cb = 0; cb < ncol; cb += P.pcap) {
       const int nb = min(P.pcap, ncol - cb);
       double* B = A + K;  // columns K .. K+nb of each row

@@ -57,39 +57,6 @@ __device__ __forceinline__ double monomial(const double* p, const int8_t* e,
   return v;
 }
 
-// L psi at p: Laplacian sum_a e_a (e_a - 1) p^(e - 2 eps_a), or the normal
-// derivative sum_a nrm_a e_a p^(e - eps_a); the normal is passed as scalars
-__device__ __forceinline__ double monomial_op(const double* p,
-                                              const int8_t* e, int d, int op,
-                                              double n0, double n1,
-                                              double n2) {
-  const int e0 = e[0], e1 = e[1], e2 = (d == 3) ? e[2] : 0;
-  const double p0 = p[0], p1 = p[1], p2 = (d == 3) ? p[2] : 1.0;
-  double s = 0.0;
-  if (op == ORBF_OP_LAPLACIAN) {
-    if (e0 >= 2)
-      s += (double)(e0 * (e0 - 1)) *
-           (ipow_small(p0, e0 - 2) * ipow_small(p1, e1) * ipow_small(p2, e2));
-    if (e1 >= 2)
-      s += (double)(e1 * (e1 - 1)) *
-           (ipow_small(p0, e0) * ipow_small(p1, e1 - 2) * ipow_small(p2, e2));
-    if (e2 >= 2)
-      s += (double)(e2 * (e2 - 1)) *
-           (ipow_small(p0, e0) * ipow_small(p1, e1) * ipow_small(p2, e2 - 2));
-  } else {
-    if (e0 >= 1)
-      s += n0 * ((double)e0 * (ipow_small(p0, e0 - 1) * ipow_small(p1, e1) *
-                               ipow_small(p2, e2)));
-    if (e1 >= 1)
-      s += n1 * ((double)e1 * (ipow_small(p0, e0) * ipow_small(p1, e1 - 1) *
-                               ipow_small(p2, e2)));
-    if (e2 >= 1)
-      s += n2 * ((double)e2 * (ipow_small(p0, e0) * ipow_small(p1, e1) *
-                               ipow_small(p2, e2 - 1)));
-  }
-  return s;
-}
-
 // sqrt(x) for x >= 0 from the hardware reciprocal-square-root estimate and
 // two Newton steps on s^2 = x (accurate to a few ulp; 0 for x = 0)
 __device__ __forceinline__ double sqrt_nr(double x) {
@@ -109,15 +76,31 @@ __device__ __forceinline__ double phs(double r2, int m) {
 }
 
 // L |x - x_j|^m at x, with (dx,dy,dz) = x - x_j and r2 = |x - x_j|^2:
-// Laplacian m (m + d - 2) r^(m-2); gradient m r^(m-2) (x - x_j) . nrm
+// Laplacian m (m + d - 2) r^(m-2); identity r^m; a first derivative along
+// the unit vector (n0, n1, n2) (normal, or e_a for d/dx_a):
+// m r^(m-2) (x - x_j) . n
 __device__ __forceinline__ double phs_op(double dx, double dy, double dz,
                                          double r2, int m, int d, int op,
                                          double n0, double n1, double n2) {
   double p = sqrt_nr(r2);  // r^(m-2), m - 2 odd
   for (int i = 0; i < (m - 3) / 2; ++i) p *= r2;
   if (op == ORBF_OP_LAPLACIAN) return (double)(m * (m + d - 2)) * p;
+  if (op == ORBF_OP_IDENTITY) return p * r2;
   const double dot = dx * n0 + dy * n1 + dz * n2;
   return ((double)m * p) * dot;
+}
+
+// 1 / rho^theta: theta = 2 (Laplacian), 0 (identity), 1 (first derivatives)
+__device__ __forceinline__ double op_unscale(int op, double rho2,
+                                             double rho) {
+  return op == ORBF_OP_LAPLACIAN ? 1.0 / rho2
+         : op == ORBF_OP_IDENTITY ? 1.0
+                                  : 1.0 / rho;
+}
+
+// direction of a d/dx_a operator: component a of e_a is 1
+__device__ __forceinline__ void op_axis(int op, double (&nrm)[3]) {
+  if (op >= ORBF_OP_DX && op <= ORBF_OP_DZ) nrm[op - ORBF_OP_DX] = 1.0;
 }
 
 // Monomials from a power table pw[a * (l + 1) + e] = p_a^e of one point.
@@ -127,7 +110,7 @@ __device__ __forceinline__ double monomial_pw(const double* pw, int l1,
 }
 
 // L psi from the power table: Laplacian sum_a e_a (e_a - 1) p^(e - 2 eps_a),
-// or the normal derivative sum_a n_a e_a p^(e - eps_a)
+// the identity p^e, or a first derivative sum_a n_a e_a p^(e - eps_a)
 __device__ __forceinline__ double monomial_op_pw(const double* pw, int l1,
                                                  const int8_t* e, int op,
                                                  double n0, double n1,
@@ -137,7 +120,9 @@ __device__ __forceinline__ double monomial_op_pw(const double* pw, int l1,
   const double* p1 = pw + l1;
   const double* p2 = pw + 2 * l1;
   double s = 0.0;
-  if (op == ORBF_OP_LAPLACIAN) {
+  if (op == ORBF_OP_IDENTITY) {
+    s = p0[e0] * p1[e1] * p2[e2];
+  } else if (op == ORBF_OP_LAPLACIAN) {
     if (e0 >= 2) s += (double)(e0 * (e0 - 1)) * (p0[e0 - 2] * p1[e1] * p2[e2]);
     if (e1 >= 2) s += (double)(e1 * (e1 - 1)) * (p0[e0] * p1[e1 - 2] * p2[e2]);
     if (e2 >= 2) s += (double)(e2 * (e2 - 1)) * (p0[e0] * p1[e1] * p2[e2 - 2]);

@@ -110,7 +110,9 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
       const int q = t / M, s = t - q * M;
       psi_s[t] = monomial_pw(pw_s + 3 * q * l1, l1, ex_s + 3 * s);
     }
-    const double sinv = 1.0 / ((op == ORBF_OP_LAPLACIAN) ? r2c : rho);
+    const double sinv = op_unscale(op, r2c, rho);
+    double nrm[3] = {0.0, 0.0, 0.0};
+    op_axis(op, nrm);
     wsync();
 
     // ---- assemble A_hat (FP64 entries, stored as FP32) ----
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
       for (int t = lane; t < nb * M; t += 64) {
         const int e = t / M, s = t - e * M;
         lpsi_s[t] = monomial_op_pw(pw_s + 3 * cols_s[cb + e] * l1, l1,
-                                   ex_s + 3 * s, op, 0.0, 0.0, 0.0);
+                                   ex_s + 3 * s, op, nrm[0], nrm[1], nrm[2]);
       }
       double X[L][PL];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
                 const double* pe = xi_s + 3 * cols_s[cb + e];
                 const double dx = pe[0] - x0, dy = pe[1] - x1, dz = pe[2] - x2;
                 b = phs_op(dx, dy, dz, dx * dx + dy * dy + dz * dz, m, d, op,
-                           0.0, 0.0, 0.0);
+                           nrm[0], nrm[1], nrm[2]);
               } else {
                 b = lpsi_s[e * M + (i - n)];
               }

@@ -87,6 +87,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
       nrm[1] = P.normals[ci * d + 1];
       if (d == 3) nrm[2] = P.normals[ci * d + 2];
     }
+    op_axis(op, nrm);
     int ncol = 0, nball = 0;
     constexpr bool accept_mode = ACC;
     if (accept_mode) {
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         acc *= v;
       }
     }
-    const double sinv = 1.0 / ((op == ORBF_OP_LAPLACIAN) ? r2c : rho);
+    const double sinv = op_unscale(op, r2c, rho);
 
     for (int cb = 0; cb < ncol; cb += 8 * PL) {
       const int nb = min(8 * PL, ncol - cb);

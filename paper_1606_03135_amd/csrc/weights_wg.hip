@@ -87,6 +87,7 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
       nrm[1] = P.normals[ci * d + 1];
       if (d == 3) nrm[2] = P.normals[ci * d + 2];
     }
+    op_axis(op, nrm);
     if (wave == 0) {
       int ncol = 0;
       if (explicit_rows) {
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
       const int qi = q / M, s = q - qi * M;
       psi_s[q] = monomial_pw(pw_s + 3 * qi * l1, l1, ex_s + 3 * s);
     }
-    const double sinv = 1.0 / ((op == ORBF_OP_LAPLACIAN) ? r2c : rho);
+    const double sinv = op_unscale(op, r2c, rho);
 
     for (int cb = 0; cb < ncol; cb += kG * PL) {
       const int nb = min(kG * PL, ncol - cb);

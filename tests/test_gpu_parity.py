@@ -364,3 +364,80 @@ def test_singular_stencils(orbf, n, l, prec):
     assert e.value.code == orbf.ESINGULAR
     W = r["W"].cpu().numpy()
     assert np.isnan(W).all()
+
+
+OP_CASES = {
+    # name: (node set, n, m, l, delta, operator, precision)
+    "ball20k_dx": ("ball", 20000, 50, 5, 3, 0.3, "DX", "fp64"),
+    "ball20k_dz": ("ball", 20000, 50, 5, 3, 0.3, "DZ", "fp64"),
+    "ball20k_id": ("ball", 20000, 50, 5, 3, 0.3, "IDENTITY", "fp64"),
+    "disk5k_dy": ("disk", 5000, 31, 5, 4, 0.5, "DY", "fp64"),
+    "disk5k_id": ("disk", 5000, 31, 5, 4, 0.5, "IDENTITY", "fp64"),
+    # n + M > 72: the four-wavefront kernel
+    "ball3k_n105_dx": ("ball", 3000, 105, 5, 4, 0.5, "DX", "fp64"),
+    # FP32 elimination + FP64 refinement
+    "ball20k_dy_fp32": ("ball", 20000, 50, 5, 3, 0.3, "DY", "fp32"),
+    # the split schedule's pass widths (N >= 65536 takes it by default)
+    "ball70k_dx": ("ball", 70000, 50, 5, 3, 0.3, "DX", "fp64"),
+}
+
+
+@pytest.mark.parametrize("case", list(OP_CASES))
+def test_operators_match_oracle(orbf, ctx, case):
+    """d/dx_a and identity DMs on the covering, against the oracle: same
+    structure bit for bit, weights within 1e-9 per row; identity rows are
+    unit vectors."""
+    kind, N, n, m, l, delta, opname, prec = OP_CASES[case]
+    op = getattr(orbf, "OP_" + opname)
+    x = nodesets.ball(N, 2)["x"] if kind == "ball" else \
+        nodesets.disk(N, 200, 1)["x"]
+    _say(f"[gpu] operator {case}: N={len(x)} n={n} op={opname} {prec}")
+    ref = oracle.build_dm(x, n, m, l, delta, op=getattr(oracle, "OP_" + opname))
+    got = orbf.build_dm(gpu(x), n, m, l, delta, op=op, ctx=ctx,
+                        prec=orbf.PREC_FP32_IR if prec == "fp32"
+                        else orbf.PREC_FP64)
+    owner = got["owner"].cpu().numpy()
+    assert np.array_equal(owner, ref["owner"])
+    assert np.array_equal(got["col"].cpu().numpy(), ref["col"])
+    W = got["W"].cpu().numpy()
+    rows = owner >= 0
+    err = row_err(W[rows], ref["W"][rows])
+    _say(f"[gpu] {case}: max row rel err {err:.2e}")
+    assert err <= TOL
+    if opname == "IDENTITY":
+        st = got["knn"].cpu().numpy()[owner]
+        unit = (st == np.arange(len(x))[:, None]).astype(float)
+        assert np.abs(W - unit).max() < 1e-9
+
+
+def test_operator_explicit_rows(orbf, ctx):
+    """d/dx rows at an explicit node list (each on its own stencil)."""
+    x = nodesets.ball(5000, 3)["x"]
+    n, m, l = 40, 5, 3
+    rows = np.arange(0, 5000, 7, dtype=np.int32)
+    idx, rho2 = oracle.knn(x, n)
+    own_ref, W_ref = oracle.center_rows(x, idx, m, l, rows, oracle.OP_DX)
+    k, r = orbf.build_nodes_knn(ctx, gpu(x), n)
+    owner = torch.full((len(x),), -1, dtype=torch.int32, device="cuda:0")
+    W = orbf.compute_weights(ctx, orbf.OP_DX, m, l, n, 1.0, gpu(x), k, r,
+                             rows=gpu(rows), owner=owner)
+    ctx.sync()
+    assert np.array_equal(owner.cpu().numpy(), own_ref)
+    err = row_err(W.cpu().numpy()[rows], W_ref[rows])
+    _say(f"[gpu] explicit d/dx rows: max row rel err {err:.2e}")
+    assert err <= TOL
+
+
+def test_operator_errors(orbf, ctx):
+    x = gpu(nodesets.disk(2000, 100, 1)["x"])
+    k, r = orbf.build_nodes_knn(ctx, x, 20)
+    c, nc, o, p = orbf.select_overlapped_stencils(ctx, x, k, r, 0.5)
+    for op, tau in ((orbf.OP_DZ, math.inf),  # d = 2
+                    (orbf.OP_NEUMANN, math.inf),  # covered rows need rows
+                    (orbf.OP_DX, 2.0),  # Lebesgue test: Laplacian only
+                    (9, math.inf)):
+        with pytest.raises(orbf.OrbfError) as e:
+            orbf.compute_weights(ctx, op, 5, 2, 20, 0.5, x, k, r, centers=c,
+                                 n_centers=nc, owner=o, tau=tau)
+        assert e.value.code == orbf.EINVAL
+    ctx.sync()
