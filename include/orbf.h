@@ -207,7 +207,7 @@ typedef struct orbf_weights_args {
  *        mode (a) only; mode (c), the Lebesgue test, with the LAPLACIAN
  *   m  : odd PHS exponent >= 3;  l : polynomial degree >= 0;
  *   n  : stencil size (>= M);    delta : overlap parameter in [0,1] (mode c)
- * Errors: EINVAL (parameters, NULL outputs, n + M > 160, mode/op mismatch),
+ * Errors: EINVAL (parameters, NULL outputs, n + M > 144, mode/op mismatch),
  * ESINGULAR at sync time (exact zero pivot; the stencil's rows are NaN). */
 orbf_status orbf_compute_weights(orbf_ctx* ctx, orbf_op op, int m, int l,
                                  int n, double delta,

@@ -285,7 +285,7 @@ orbf_status orbf_compute_weights(orbf_ctx* ctx, orbf_op op, int m, int l,
   if (l < 0) return fail(ctx, ORBF_EINVAL, "polynomial degree l < 0");
   const int M = num_monomials(a->d, l);
   if (n < M) return fail(ctx, ORBF_EINVAL, "stencil size n < C(l+d, d)");
-  if (n + M > 160) return fail(ctx, ORBF_EINVAL, "n + M > 160");
+  if (n + M > 144) return fail(ctx, ORBF_EINVAL, "n + M > 144");
   if (!(delta >= 0.0 && delta <= 1.0))
     return fail(ctx, ORBF_EINVAL, "delta must lie in [0, 1]");
   if (!(a->tau >= 1.0)) return fail(ctx, ORBF_EINVAL, "tau must be >= 1");
@@ -331,8 +331,8 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
 orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,
                               orbf_schedule schedule) {
   if (!ctx) return ORBF_EINVAL;
-  if (K < 1 || K > 160 || pclass < 0 || pclass > 1)
-    return fail(ctx, ORBF_EINVAL, "schedule: K in 1..160, pclass 0 or 1");
+  if (K < 1 || K > 144 || pclass < 0 || pclass > 1)
+    return fail(ctx, ORBF_EINVAL, "schedule: K in 1..144, pclass 0 or 1");
   if ((schedule == ORBF_SCHED_WAVE16 || schedule == ORBF_SCHED_WAVE8 ||
        schedule == ORBF_SCHED_SPLIT) &&
       K > 72)

@@ -490,8 +490,7 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   // cell order (row qs belongs to node perm[qs]): contiguous writes
   auto* d2 = (double*)scratch(ctx, B_KNN_D2, (size_t)N * n * 8, &st);
   if (st) return st;
-  double alpha = 0.9;
-  if (const char* e = getenv("ORBF_KNN_ALPHA")) alpha = atof(e);
+  const double alpha = 0.9;  // cell side in units of the mean stencil radius
   hipStream_t s = ctx->stream;
   const unsigned g1 = (unsigned)((N + 255) / 256);
   hipLaunchKernelGGL(bbox_partial_kernel, dim3(nblk), dim3(256), 0, s, xyz, N,

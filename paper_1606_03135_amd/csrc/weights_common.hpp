@@ -40,7 +40,7 @@ struct WeightsParams {
   int32_t* fb_list;
   int64_t* fb_count;
   DevStatus* st;
-  int d, n, m, l, M, K, op, pcap, ldm;
+  int d, n, m, l, M, K, op;
 };
 
 __device__ __forceinline__ double ipow_small(double v, int e) {

@@ -229,6 +229,15 @@ def test_errors(orbf, ctx):
         orbf.compute_weights(ctx, orbf.OP_LAPLACIAN, 3, 4, 8, 0.5, gpu(x), k,
                              r, centers=c, n_centers=nc, owner=o)
     ctx.sync()
+    # n + M > 144: no kernel serves it
+    x3 = gpu(nodesets.ball(400, 1)["x"])
+    k3, r3 = orbf.build_nodes_knn(ctx, x3, 120)
+    c3, nc3, o3, p3 = orbf.select_overlapped_stencils(ctx, x3, k3, r3, 0.5)
+    with pytest.raises(orbf.OrbfError) as e:
+        orbf.compute_weights(ctx, orbf.OP_LAPLACIAN, 5, 4, 120, 0.5, x3, k3,
+                             r3, centers=c3, n_centers=nc3, owner=o3)
+    assert e.value.code == orbf.EINVAL
+    ctx.sync()
 
 
 def test_bitwise_repeatable(orbf, ctx):
