@@ -253,6 +253,26 @@ def csr(knn_idx, owner, W):
     return row_ptr, col[:nnz].copy(), val[:nnz].copy()
 
 
+def gershgorin(row_ptr, col, val):
+    """Gershgorin disks of the DM rows (Sec. 4.2.1): center L_kk and radius
+    g_k = sum_{j != k} |L_kj| per row (0 and 0 for an empty row), and the
+    summary (max_k L_kk + g_k, min_k L_kk - g_k, number of rows whose disk
+    reaches Re > 0).  Plain definition, one row at a time."""
+    N = len(row_ptr) - 1
+    diag = np.zeros(N)
+    radius = np.zeros(N)
+    for k in range(N):
+        for t in range(int(row_ptr[k]), int(row_ptr[k + 1])):
+            if col[t] == k:
+                diag[k] = val[t]
+            else:
+                radius[k] += abs(val[t])
+    right = diag + radius
+    left = diag - radius
+    return diag, radius, (float(right.max()), float(left.min()),
+                          int((right > 0).sum()))
+
+
 def build_dm(x, n, m, l, delta, tau=np.inf, eligible=None, boundary=None,
              normals=None, nthreads=0, knn_method="auto", op=OP_LAPLACIAN):
     """Whole oracle pipeline: stencils, covering (+Lebesgue), interior rows

@@ -85,3 +85,40 @@ def test_gershgorin_identity_and_csr(disk_small):
     Lf = np.add.reduceat(val * f[col], rp[:-1])
     ref = np.einsum("ij,ij->i", R["W"], f[idx[owner]])
     assert np.allclose(Lf, ref, rtol=1e-12, atol=1e-9)
+
+
+def test_gershgorin_disks_contain_the_spectrum():
+    """Gershgorin circle theorem on small DMs: every eigenvalue of L lies in
+    the union of the row disks, and the disk radius is the row's
+    L-Lebesgue value minus |L_kk| (Sec. 4.2.1)."""
+    for x, n, l, delta, tau in ((nodesets.square(22, 0), 12, 2, 0.5, np.inf),
+                                (nodesets.square(22, 1), 12, 2, 0.2, 1.0)):
+        R = oracle.build_dm(x, n, 3, l, delta, tau=tau)
+        diag, radius, summ = oracle.gershgorin(R["row_ptr"], R["col"],
+                                               R["val"])
+        assert np.allclose(radius, R["lam"] - np.abs(diag), rtol=1e-12,
+                           atol=1e-12 * R["lam"].max())
+        N = len(x)
+        L = np.zeros((N, N))
+        for k in range(N):
+            s0, s1 = R["row_ptr"][k], R["row_ptr"][k + 1]
+            L[k, R["col"][s0:s1]] = R["val"][s0:s1]
+        ev = np.linalg.eigvals(L)
+        slack = 1e-9 * np.abs(L).sum(1).max()
+        inside = (np.abs(ev[:, None] - diag[None, :]) <=
+                  radius[None, :] + slack).any(1)
+        assert inside.all()
+        assert summ[0] >= ev.real.max() - slack  # the union bounds Re(lambda)
+        assert summ[1] <= ev.real.min() + slack
+        assert summ[2] == int((diag + radius > 0).sum())
+
+
+def test_gershgorin_small_matrix():
+    """Hand-checked disks of a 3 x 3 CSR matrix with an empty row."""
+    rp = np.array([0, 2, 2, 5])
+    col = np.array([0, 2, 0, 1, 2], np.int32)
+    val = np.array([-4.0, 1.5, 2.0, -3.0, 0.5])
+    d, r, s = oracle.gershgorin(rp, col, val)
+    assert np.array_equal(d, [-4.0, 0.0, 0.5])
+    assert np.array_equal(r, [1.5, 0.0, 5.0])
+    assert s == (5.5, -5.5, 1)
