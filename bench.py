@@ -194,6 +194,24 @@ def bench_ball(args, torch, orbf, nodesets):
                      "flops_per_launch": flops_launch,
                      "launch_ms": wk_ms},
     }
+    # Gershgorin disks of the built DM (Sec. 4.2.1): a diagnostic pass over
+    # the CSR, timed on its own after the builds
+    e0, e1 = torch.cuda.Event(enable_timing=True), \
+        torch.cuda.Event(enable_timing=True)
+    orbf.gershgorin(ctx, r["row_ptr"], r["col"], r["val"])
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        _, _, gs = orbf.gershgorin(ctx, r["row_ptr"], r["col"], r["val"])
+    e1.record()
+    torch.cuda.synchronize()
+    gms = e0.elapsed_time(e1) / 10
+    gs = gs.cpu().numpy()
+    out["gershgorin"] = {"ms": gms, "max_right_edge": float(gs[0]),
+                         "min_left_edge": float(gs[1]),
+                         "rows_reaching_positive_re": int(gs[2]),
+                         "hbm_gbs": (nnz * 12 + (N + 1) * 8) / (gms * 1e-3)
+                         / 1e9}
     if not args.no_fp32:
         W64 = r["W"].clone()
         steps32 = max(3, args.steps // 5)

@@ -223,6 +223,22 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
                               const double* W, int64_t* row_ptr, int32_t* col,
                               double* val);
 
+/* Gershgorin disks of a DM in CSR (Sec. 4.2.1, "Improving stability"): row
+ * k's disk has center L_kk and radius g_k = sum_{j != k} |L_kj| (for a DM
+ * row, its L-Lebesgue value minus |L_kk|); every eigenvalue of L lies in
+ * their union, so no eigenvalue can have a positive real part unless some
+ * disk reaches past 0.  An empty row has center 0 and radius 0.
+ *   row_ptr, col, val : the CSR (device; as from orbf_assemble_csr)
+ *   diag, radius      : N FP64 outputs (device), each may be NULL
+ *   summary           : 3 FP64 outputs (device): max_k (L_kk + g_k),
+ *                       min_k (L_kk - g_k), and the number of rows with
+ *                       L_kk + g_k > 0
+ * The radii are sums in an order of the library's choosing (deterministic
+ * for a given N).  Errors: EINVAL (N out of range, NULL input or summary). */
+orbf_status orbf_gershgorin(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
+                            const int32_t* col, const double* val,
+                            double* diag, double* radius, double* summary);
+
 /* Kernel schedules for the weights.  Stencils of one system size K = n + M
  * are solved by one of these kernels; which is fastest depends on K and on
  * how many rows a stencil keeps, estimated as n (1-delta)^d: p-class 0 for

@@ -109,6 +109,8 @@ def lib():
         L.orbf_compute_weights.restype = _I
         L.orbf_assemble_csr.argtypes = [_P, _I64, _I, _P, _P, _P, _P, _P, _P]
         L.orbf_assemble_csr.restype = _I
+        L.orbf_gershgorin.argtypes = [_P, _I64, _P, _P, _P, _P, _P, _P]
+        L.orbf_gershgorin.restype = _I
         L.orbf_phase_times.argtypes = [_P, ctypes.POINTER(_D)]
         L.orbf_phase_times.restype = _I
         L.orbf_build_dm_batched.argtypes = [_P, ctypes.POINTER(SetDesc), _I]
@@ -296,6 +298,26 @@ def assemble_csr(ctx, knn, owner, W):
                                       _ptr(W), _ptr(row_ptr), _ptr(col),
                                       _ptr(val)))
     return row_ptr, col, val
+
+
+def gershgorin(ctx, row_ptr, col, val, rows=True):
+    """Gershgorin disks of a DM in CSR (Sec. 4.2.1): per-row centers L_kk
+    and radii sum_{j != k} |L_kj| (None unless ``rows``), and the summary
+    tensor [max_k L_kk + g_k, min_k L_kk - g_k, rows with L_kk + g_k > 0]."""
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    val = _dev(val, torch.float64, "val")
+    N = row_ptr.numel() - 1
+    dev = row_ptr.device
+    diag = radius = None
+    if rows:
+        diag = torch.empty(N, dtype=torch.float64, device=dev)
+        radius = torch.empty(N, dtype=torch.float64, device=dev)
+    summary = torch.empty(3, dtype=torch.float64, device=dev)
+    ctx.check(lib().orbf_gershgorin(ctx._h, N, _ptr(row_ptr), _ptr(col),
+                                    _ptr(val), _ptr(diag), _ptr(radius),
+                                    _ptr(summary)))
+    return diag, radius, summary
 
 
 def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,

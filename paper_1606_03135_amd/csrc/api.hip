@@ -239,6 +239,7 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   t += want(Nn * (size_t)n);            // B_CSR_RANK
   t += want(Nn * 12) + want(24);        // B_CLASS, B_CLASS_N
   t += want(Nn * 4);                    // B_P_CACHE
+  t += want(gershgorin_scratch_bytes()); // B_GERSH
   return t;
 }
 
@@ -326,6 +327,17 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
   hipSetDevice(ctx->device);
   PhaseTimer tm(ctx, 3);
   return launch_csr(ctx, N, n, knn, owner, W, row_ptr, col, val);
+}
+
+orbf_status orbf_gershgorin(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
+                            const int32_t* col, const double* val,
+                            double* diag, double* radius, double* summary) {
+  if (!ctx) return ORBF_EINVAL;
+  if (N < 1 || N > INT32_MAX) return fail(ctx, ORBF_EINVAL, "N out of range");
+  if (!row_ptr || !col || !val || !summary)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  hipSetDevice(ctx->device);
+  return launch_gershgorin(ctx, N, row_ptr, col, val, diag, radius, summary);
 }
 
 orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,

@@ -159,6 +159,7 @@ enum BufId {
   B_CLASS,
   B_CLASS_N,
   B_P_CACHE,
+  B_GERSH,
   B_NUM,
 };
 static_assert(B_NUM <= 32, "orbf_ctx::buf holds 32 scratch buffers");
@@ -184,6 +185,11 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
                          int64_t* n_centers, int32_t* owner, int32_t* p);
 orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
                            double t2, const orbf_weights_args* a);
+size_t gershgorin_scratch_bytes();
+orbf_status launch_gershgorin(orbf_ctx* ctx, int64_t N,
+                              const int64_t* row_ptr, const int32_t* col,
+                              const double* val, double* diag, double* radius,
+                              double* summary);
 orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        const int32_t* owner, const double* W,
                        int64_t* row_ptr, int32_t* col, double* val);

@@ -450,3 +450,39 @@ def test_operator_errors(orbf, ctx):
                                  n_centers=nc, owner=o, tau=tau)
         assert e.value.code == orbf.EINVAL
     ctx.sync()
+
+
+@pytest.mark.parametrize("case", ["disk5k_d05_tau5", "ball20k_d03"])
+def test_gershgorin_matches_oracle(orbf, ctx, case):
+    """Gershgorin disks of the GPU-built DM against the oracle's plain
+    definition on the same CSR: centers exact, radii to 1e-12 of the row's
+    absolute sum, summary consistent with the rows."""
+    x, el, bnd, nrm, c = make(case)
+    got = orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"],
+                        tau=c.get("tau", math.inf),
+                        eligible=None if el is None else gpu(el),
+                        boundary=None if bnd is None else gpu(bnd),
+                        normals=None if nrm is None else gpu(nrm), ctx=ctx)
+    diag, radius, summ = orbf.gershgorin(ctx, got["row_ptr"], got["col"],
+                                         got["val"])
+    ctx.sync()
+    rp = got["row_ptr"].cpu().numpy()
+    col = got["col"].cpu().numpy()
+    val = got["val"].cpu().numpy()
+    d_ref, r_ref, s_ref = oracle.gershgorin(rp, col, val)
+    d = diag.cpu().numpy()
+    r = radius.cpu().numpy()
+    s = summ.cpu().numpy()
+    rowsum = np.add.reduceat(np.abs(val), rp[:-1])
+    _say(f"[gpu] gershgorin {case}: max right edge {s[0]:.3e}, "
+         f"rows reaching Re > 0: {int(s[2])}")
+    assert np.array_equal(d, d_ref)
+    assert np.all(np.abs(r - r_ref) <= 1e-12 * rowsum)
+    assert s[0] == (d + r).max() and s[1] == (d - r).min()
+    assert int(s[2]) == int((d + r > 0).sum())
+    scale = rowsum.max()
+    assert abs(s[0] - s_ref[0]) <= 1e-12 * scale
+    assert abs(s[1] - s_ref[1]) <= 1e-12 * scale
+    # a row whose edge is within rounding of 0 may count either way
+    near = int((np.abs(d_ref + r_ref) <= 1e-12 * rowsum).sum())
+    assert abs(int(s[2]) - s_ref[2]) <= near
