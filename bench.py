@@ -212,6 +212,19 @@ def bench_ball(args, torch, orbf, nodesets):
                          "rows_reaching_positive_re": int(gs[2]),
                          "hbm_gbs": (nnz * 12 + (N + 1) * 8) / (gms * 1e-3)
                          / 1e9}
+    # y = L x with the built DM: the product its consumers (time stepping,
+    # Krylov solves) are made of, timed on its own after the builds
+    xv = torch.rand(N, dtype=torch.float64, device=dev)
+    yv = orbf.spmv(ctx, r["row_ptr"], r["col"], r["val"], xv)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(20):
+        orbf.spmv(ctx, r["row_ptr"], r["col"], r["val"], xv, yv)
+    e1.record()
+    torch.cuda.synchronize()
+    sms = e0.elapsed_time(e1) / 20
+    out["spmv"] = {"ms": sms, "hbm_gbs": (nnz * 12 + (N + 1) * 8 + N * 16)
+                   / (sms * 1e-3) / 1e9}
     if not args.no_fp32:
         W64 = r["W"].clone()
         steps32 = max(3, args.steps // 5)

@@ -223,6 +223,18 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
                               const double* W, int64_t* row_ptr, int32_t* col,
                               double* val);
 
+/* y = L x for a DM in CSR: the discrete operator applied to nodal values
+ * x (Sec. 4.1: (L f)(x_i) is approximated by sum_j L_ij f(x_j)), the
+ * product every use of the DM (time stepping, Krylov solves, Sec. 5) is
+ * built on.
+ *   row_ptr, col, val : the CSR (device; as from orbf_assemble_csr)
+ *   x : N FP64 input (device; indexed by col);  y : N FP64 output (device)
+ * Each y[i] sums its row's products in a fixed order (deterministic).
+ * Errors: EINVAL (N out of range, NULL pointer, x == y). */
+orbf_status orbf_spmv(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
+                      const int32_t* col, const double* val, const double* x,
+                      double* y);
+
 /* Gershgorin disks of a DM in CSR (Sec. 4.2.1, "Improving stability"): row
  * k's disk has center L_kk and radius g_k = sum_{j != k} |L_kj| (for a DM
  * row, its L-Lebesgue value minus |L_kk|); every eigenvalue of L lies in

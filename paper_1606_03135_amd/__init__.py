@@ -109,6 +109,8 @@ def lib():
         L.orbf_compute_weights.restype = _I
         L.orbf_assemble_csr.argtypes = [_P, _I64, _I, _P, _P, _P, _P, _P, _P]
         L.orbf_assemble_csr.restype = _I
+        L.orbf_spmv.argtypes = [_P, _I64, _P, _P, _P, _P, _P]
+        L.orbf_spmv.restype = _I
         L.orbf_gershgorin.argtypes = [_P, _I64, _P, _P, _P, _P, _P, _P]
         L.orbf_gershgorin.restype = _I
         L.orbf_phase_times.argtypes = [_P, ctypes.POINTER(_D)]
@@ -298,6 +300,20 @@ def assemble_csr(ctx, knn, owner, W):
                                       _ptr(W), _ptr(row_ptr), _ptr(col),
                                       _ptr(val)))
     return row_ptr, col, val
+
+
+def spmv(ctx, row_ptr, col, val, x, y=None):
+    """y = L x for a DM in CSR (device tensors); returns y."""
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    val = _dev(val, torch.float64, "val")
+    x = _dev(x, torch.float64, "x")
+    N = row_ptr.numel() - 1
+    if y is None:
+        y = torch.empty(N, dtype=torch.float64, device=x.device)
+    ctx.check(lib().orbf_spmv(ctx._h, N, _ptr(row_ptr), _ptr(col), _ptr(val),
+                              _ptr(x), _ptr(y)))
+    return y
 
 
 def gershgorin(ctx, row_ptr, col, val, rows=True):

@@ -329,6 +329,18 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
   return launch_csr(ctx, N, n, knn, owner, W, row_ptr, col, val);
 }
 
+orbf_status orbf_spmv(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
+                      const int32_t* col, const double* val, const double* x,
+                      double* y) {
+  if (!ctx) return ORBF_EINVAL;
+  if (N < 1 || N > INT32_MAX) return fail(ctx, ORBF_EINVAL, "N out of range");
+  if (!row_ptr || !col || !val || !x || !y)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  if (x == y) return fail(ctx, ORBF_EINVAL, "x and y must not alias");
+  hipSetDevice(ctx->device);
+  return launch_spmv(ctx, N, row_ptr, col, val, x, y);
+}
+
 orbf_status orbf_gershgorin(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
                             const int32_t* col, const double* val,
                             double* diag, double* radius, double* summary) {

@@ -77,7 +77,35 @@ __global__ __launch_bounds__(256) void csr_scatter_kernel(
   }
 }
 
+// y = L x for a CSR matrix: sixteen lanes per row, a grid-stride over rows;
+// each row's products are summed in a fixed order (lane partials, then a
+// butterfly over the sixteen lanes), so y is deterministic.
+__global__ __launch_bounds__(256) void spmv_kernel(
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const double* __restrict__ x, int64_t N,
+    double* __restrict__ y) {
+  const int pl = threadIdx.x & 15;
+  for (int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4; e < N;
+       e += (int64_t)gridDim.x * 16) {
+    const int64_t s0 = row_ptr[e], s1 = row_ptr[e + 1];
+    double acc = 0.0;
+    for (int64_t t = s0 + pl; t < s1; t += 16) acc = fma(val[t], x[col[t]], acc);
+    for (int o = 1; o < 16; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    if (pl == 0) y[e] = acc;
+  }
+}
+
 }  // namespace
+
+orbf_status launch_spmv(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
+                        const int32_t* col, const double* val,
+                        const double* x, double* y) {
+  const int64_t want = (N + 15) / 16;
+  const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
+  hipLaunchKernelGGL(spmv_kernel, dim3(blocks), dim3(256), 0, ctx->stream,
+                     row_ptr, col, val, x, N, y);
+  return hip_check(ctx, hipGetLastError(), "spmv");
+}
 
 orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        const int32_t* owner, const double* W,

@@ -185,6 +185,9 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
                          int64_t* n_centers, int32_t* owner, int32_t* p);
 orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
                            double t2, const orbf_weights_args* a);
+orbf_status launch_spmv(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
+                        const int32_t* col, const double* val,
+                        const double* x, double* y);
 size_t gershgorin_scratch_bytes();
 orbf_status launch_gershgorin(orbf_ctx* ctx, int64_t N,
                               const int64_t* row_ptr, const int32_t* col,
