@@ -225,6 +225,27 @@ def bench_ball(args, torch, orbf, nodesets):
     sms = e0.elapsed_time(e1) / 20
     out["spmv"] = {"ms": sms, "hbm_gbs": (nnz * 12 + (N + 1) * 8 + N * 16)
                    / (sms * 1e-3) / 1e9}
+    # one backward-Euler step of u_t = Laplacian u with the built DM
+    # (Sec. 5): (I - dt L) u1 = u0 inside, u1 = 0 on the unit sphere's
+    # nodes, dt = 1e-5, from a Gaussian bump, solved to 1e-10 by BiCGSTAB
+    kind = torch.from_numpy(
+        (np.sqrt((x * x).sum(1)) < 1.0 - 1e-12).astype(np.uint8)).to(dev)
+    u0 = torch.from_numpy(np.exp(-4.0 * (x * x).sum(1))).to(dev)
+    b = u0 * kind.to(torch.float64)
+    orbf.solve_implicit(ctx, r["row_ptr"], r["col"], r["val"], b,
+                        beta=-1e-5, row_kind=kind, x0=u0, tol=1e-10,
+                        max_iter=10)  # warm: scratch and pinned scalars
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, res = orbf.solve_implicit(ctx, r["row_ptr"], r["col"], r["val"],
+                                      b, beta=-1e-5, row_kind=kind, x0=u0,
+                                      tol=1e-10, max_iter=1000)
+    torch.cuda.synchronize()
+    ims = 1e3 * (time.perf_counter() - t0)
+    out["implicit_step"] = {"ms": ims, "iterations": its, "relres": res,
+                            "ms_per_iteration": ims / max(its, 1),
+                            "dt": 1e-5, "tol": 1e-10,
+                            "dirichlet_rows": int(N - kind.sum().item())}
     if not args.no_fp32:
         W64 = r["W"].clone()
         steps32 = max(3, args.steps // 5)

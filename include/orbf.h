@@ -251,6 +251,38 @@ orbf_status orbf_gershgorin(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
                             const int32_t* col, const double* val,
                             double* diag, double* radius, double* summary);
 
+/* One implicit time step with a DM (Sec. 5, "Time-Stepping": the backward
+ * Euler system whose interior block is I - nu dt L and whose boundary rows
+ * impose the boundary condition): solve A x = b, where row e of A is
+ *   row_kind[e] == 1 : alpha x_e + beta (L x)_e   (interior; backward Euler
+ *                      has alpha = 1, beta = -nu dt)
+ *   row_kind[e] == 0 : x_e                        (Dirichlet)
+ *   any other value  : (L x)_e                    (a boundary-operator row
+ *                      of the DM, e.g. a normal derivative for Neumann data)
+ * by unpreconditioned BiCGSTAB (van der Vorst 1992), started from x.
+ *   row_ptr, col, val : the CSR of L (device; as from orbf_assemble_csr)
+ *   row_kind : N bytes (device), or NULL for all rows interior
+ *   b        : N FP64 right-hand side (device);  x : N FP64 (device), in:
+ *              the initial guess (e.g. the previous time level), out: the
+ *              solution
+ *   tol      : stop when ||b - A x||_2 <= tol ||b||_2 (the recurrence
+ *              residual; ||b|| = 0 is taken as 1)
+ *   max_iter : iteration limit;  iters, relres : host outputs (each may be
+ *              NULL): iterations done and the final relative residual
+ * Synchronous: returns after the solve, reading four inner products back
+ * to the host per iteration; every inner product is summed in a fixed
+ * order, so a solve is deterministic.  Not converging within max_iter, or a
+ * BiCGSTAB breakdown, is not an error: relres says how far it got.  Scratch:
+ * 7 N FP64 plus 16 KB of the context.
+ * Errors: EINVAL (N out of range, NULL input, b == x, tol < 0 or NaN,
+ * max_iter < 0, alpha or beta not finite), ENOMEM, EHIP. */
+orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
+                                const int64_t* row_ptr, const int32_t* col,
+                                const double* val, const uint8_t* row_kind,
+                                double alpha, double beta, const double* b,
+                                double* x, double tol, int max_iter,
+                                int* iters, double* relres);
+
 /* Kernel schedules for the weights.  Stencils of one system size K = n + M
  * are solved by one of these kernels; which is fastest depends on K and on
  * how many rows a stencil keeps, estimated as n (1-delta)^d: p-class 0 for

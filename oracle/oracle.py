@@ -273,6 +273,35 @@ def gershgorin(row_ptr, col, val):
                           int((right > 0).sum()))
 
 
+def implicit_system(row_ptr, col, val, row_kind, alpha, beta):
+    """The matrix of one implicit time step with a DM (Sec. 5): interior
+    rows (row_kind 1) are alpha e_k + beta L_k, so backward Euler's block
+    I - nu dt L_ii, -nu dt L_ib for alpha = 1, beta = -nu dt; Dirichlet rows
+    (row_kind 0) are e_k; any other row_kind keeps the DM row L_k (a
+    boundary operator such as a normal derivative).  ``row_kind`` None
+    means every row is interior.  Returns a scipy CSR matrix."""
+    import scipy.sparse as sps
+    N = len(row_ptr) - 1
+    L = sps.csr_matrix((val, col, row_ptr), shape=(N, N))
+    kind = np.ones(N, np.uint8) if row_kind is None else np.asarray(row_kind)
+    interior = (kind == 1).astype(float)
+    dirichlet = (kind == 0).astype(float)
+    other = 1.0 - interior - dirichlet
+    eye = sps.identity(N, format="csr")
+    A = (sps.diags(interior) @ (alpha * eye + beta * L)
+         + sps.diags(dirichlet) @ eye + sps.diags(other) @ L)
+    return A.tocsr()
+
+
+def solve_implicit(row_ptr, col, val, b, row_kind=None, alpha=1.0,
+                   beta=-1.0):
+    """x = A^{-1} b for the matrix of ``implicit_system`` (Sec. 5), by a
+    direct sparse LU solve (SuperLU)."""
+    import scipy.sparse.linalg as spl
+    A = implicit_system(row_ptr, col, val, row_kind, alpha, beta)
+    return spl.spsolve(A.tocsc(), np.asarray(b, dtype=float))
+
+
 def build_dm(x, n, m, l, delta, tau=np.inf, eligible=None, boundary=None,
              normals=None, nthreads=0, knn_method="auto", op=OP_LAPLACIAN):
     """Whole oracle pipeline: stencils, covering (+Lebesgue), interior rows

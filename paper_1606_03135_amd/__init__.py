@@ -113,6 +113,10 @@ def lib():
         L.orbf_spmv.restype = _I
         L.orbf_gershgorin.argtypes = [_P, _I64, _P, _P, _P, _P, _P, _P]
         L.orbf_gershgorin.restype = _I
+        L.orbf_solve_implicit.argtypes = [
+            _P, _I64, _P, _P, _P, _P, _D, _D, _P, _P, _D, _I,
+            ctypes.POINTER(_I), ctypes.POINTER(_D)]
+        L.orbf_solve_implicit.restype = _I
         L.orbf_phase_times.argtypes = [_P, ctypes.POINTER(_D)]
         L.orbf_phase_times.restype = _I
         L.orbf_build_dm_batched.argtypes = [_P, ctypes.POINTER(SetDesc), _I]
@@ -334,6 +338,37 @@ def gershgorin(ctx, row_ptr, col, val, rows=True):
                                     _ptr(val), _ptr(diag), _ptr(radius),
                                     _ptr(summary)))
     return diag, radius, summary
+
+
+def solve_implicit(ctx, row_ptr, col, val, b, *, alpha=1.0, beta=-1.0,
+                   row_kind=None, x0=None, tol=1e-10, max_iter=1000):
+    """One implicit time step with a DM (Sec. 5): solve A x = b with row e
+    of A equal to alpha x_e + beta (L x)_e where row_kind[e] == 1 (or
+    everywhere if ``row_kind`` is None), x_e where it is 0 (Dirichlet) and
+    (L x)_e elsewhere, by BiCGSTAB from ``x0`` (zeros if None).  Returns
+    (x, iterations, relative residual)."""
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    val = _dev(val, torch.float64, "val")
+    b = _dev(b, torch.float64, "b")
+    N = row_ptr.numel() - 1
+    if b.numel() != N:
+        raise ValueError("b must have one entry per DM row")
+    if row_kind is not None:
+        row_kind = _dev(row_kind, torch.uint8, "row_kind")
+        if row_kind.numel() != N:
+            raise ValueError("row_kind must have one entry per DM row")
+    x = (torch.zeros_like(b) if x0 is None
+         else _dev(x0, torch.float64, "x0").clone())
+    if x.numel() != N:
+        raise ValueError("x0 must have one entry per DM row")
+    it = _I(0)
+    res = _D(0.0)
+    ctx.check(lib().orbf_solve_implicit(
+        ctx._h, N, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(row_kind),
+        float(alpha), float(beta), _ptr(b), _ptr(x), float(tol),
+        int(max_iter), ctypes.byref(it), ctypes.byref(res)))
+    return x, it.value, res.value
 
 
 def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,

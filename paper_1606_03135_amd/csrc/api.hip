@@ -146,6 +146,8 @@ orbf_status orbf_create(int device, void* hip_stream, size_t hbm_budget_bytes,
       hipHostMalloc((void**)&ctx->status_host, sizeof(DevStatus),
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&ctx->host_counter, sizeof(int64_t),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->host_scalars, 4 * sizeof(double),
                     hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return ORBF_ENOMEM;
@@ -170,6 +172,7 @@ void orbf_destroy(orbf_ctx* ctx) {
   if (ctx->status) hipFree(ctx->status);
   if (ctx->status_host) hipHostFree(ctx->status_host);
   if (ctx->host_counter) hipHostFree(ctx->host_counter);
+  if (ctx->host_scalars) hipHostFree(ctx->host_scalars);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);
   if (ctx->owns_stream && ctx->stream) hipStreamDestroy(ctx->stream);
@@ -214,7 +217,7 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   // Every scratch buffer is grow-only and rounded up by scratch(); the sum
   // over buffer ids of the largest request each id sees in a build bounds
   // what a context holds (kNN, covering with or without the Lebesgue test,
-  // weights in either precision, CSR).
+  // weights in either precision, CSR, Gershgorin disks, implicit solve).
   auto want = [](size_t b) { return (b ? b : 8) + (b ? b : 8) / 8 + 256; };
   const size_t Nn = (size_t)N;
   const size_t edges = Nn * (size_t)(n > 1 ? n - 1 : 1);
@@ -240,6 +243,7 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   t += want(Nn * 12) + want(24);        // B_CLASS, B_CLASS_N
   t += want(Nn * 4);                    // B_P_CACHE
   t += want(gershgorin_scratch_bytes()); // B_GERSH
+  t += want(krylov_scratch_bytes(N));   // B_KRYLOV
   return t;
 }
 
@@ -350,6 +354,26 @@ orbf_status orbf_gershgorin(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
     return fail(ctx, ORBF_EINVAL, "NULL pointer");
   hipSetDevice(ctx->device);
   return launch_gershgorin(ctx, N, row_ptr, col, val, diag, radius, summary);
+}
+
+orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
+                                const int64_t* row_ptr, const int32_t* col,
+                                const double* val, const uint8_t* row_kind,
+                                double alpha, double beta, const double* b,
+                                double* x, double tol, int max_iter,
+                                int* iters, double* relres) {
+  if (!ctx) return ORBF_EINVAL;
+  if (N < 1 || N > INT32_MAX) return fail(ctx, ORBF_EINVAL, "N out of range");
+  if (!row_ptr || !col || !val || !b || !x)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  if (b == x) return fail(ctx, ORBF_EINVAL, "b and x must not alias");
+  if (!(tol >= 0.0) || max_iter < 0)
+    return fail(ctx, ORBF_EINVAL, "tol >= 0 and max_iter >= 0 required");
+  if (!isfinite(alpha) || !isfinite(beta))
+    return fail(ctx, ORBF_EINVAL, "alpha and beta must be finite");
+  hipSetDevice(ctx->device);
+  return launch_solve_implicit(ctx, N, row_ptr, col, val, row_kind, alpha,
+                               beta, b, x, tol, max_iter, iters, relres);
 }
 
 orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,

@@ -1,0 +1,233 @@
+// Implicit time step with the DM (Sec. 5): solve A x = b where, for a DM L
+// in CSR, row e of A is chosen by row_kind[e]:
+//   1 (interior): alpha x_e + beta (L x)_e
+//   0 (Dirichlet): x_e
+//   2 (boundary operator): (L x)_e, e.g. a normal-derivative row
+// With alpha = 1 and beta = -nu dt this is the backward-Euler system of
+// Sec. 5 (BDF4 takes beta = -(12/25) nu dt): interior rows of I - nu dt L,
+// boundary rows that impose the boundary condition.
+//
+// BiCGSTAB (van der Vorst, 1992) without preconditioning.  Products with A
+// use sixteen lanes per row; every inner product is summed in a fixed
+// order (per-block partials, then one wavefront), so a solve is
+// deterministic.  The host drives the iteration and reads each inner
+// product back (pinned memory), four times per iteration.
+#include "orbf_internal.hpp"
+
+namespace orbf {
+
+namespace {
+
+constexpr int kDotBlocks = 1024;
+
+__global__ __launch_bounds__(256) void apply_kernel(
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const uint8_t* __restrict__ row_kind,
+    double alpha, double beta, const double* __restrict__ x, int64_t N,
+    double* __restrict__ y) {
+  const int pl = threadIdx.x & 15;
+  for (int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4; e < N;
+       e += (int64_t)gridDim.x * 16) {
+    const int kind = row_kind ? row_kind[e] : 1;
+    double acc = 0.0;
+    if (kind != 0) {
+      const int64_t s0 = row_ptr[e], s1 = row_ptr[e + 1];
+      for (int64_t t = s0 + pl; t < s1; t += 16)
+        acc = fma(val[t], x[col[t]], acc);
+    }
+    for (int o = 1; o < 16; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    if (pl == 0)
+      y[e] = kind == 1 ? fma(beta, acc, alpha * x[e]) : kind == 0 ? x[e] : acc;
+  }
+}
+
+// partials of a.b and (if c) c.d, one pair per block
+__global__ __launch_bounds__(256) void dot2_kernel(
+    const double* __restrict__ a, const double* __restrict__ b,
+    const double* __restrict__ c, const double* __restrict__ d, int64_t N,
+    double* __restrict__ part) {
+  __shared__ double s1[4], s2[4];
+  double u = 0.0, w = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    u = fma(a[i], b[i], u);
+    if (c) w = fma(c[i], d[i], w);
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    u += __shfl_xor(u, o, 64);
+    w += __shfl_xor(w, o, 64);
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s1[wv] = u;
+    s2[wv] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ((s1[0] + s1[1]) + s1[2]) + s1[3];
+    part[2 * blockIdx.x + 1] = ((s2[0] + s2[1]) + s2[2]) + s2[3];
+  }
+}
+
+__global__ __launch_bounds__(64) void dot2_final_kernel(
+    const double* __restrict__ part, int nparts, double* __restrict__ out) {
+  double u = 0.0, w = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 64) {
+    u += part[2 * i];
+    w += part[2 * i + 1];
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    u += __shfl_xor(u, o, 64);
+    w += __shfl_xor(w, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = u;
+    out[1] = w;
+  }
+}
+
+// r = b - y, rh = r, p = v = 0
+__global__ __launch_bounds__(256) void bicg_init_kernel(
+    const double* __restrict__ b, const double* __restrict__ y, int64_t N,
+    double* __restrict__ r, double* __restrict__ rh, double* __restrict__ p,
+    double* __restrict__ v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    const double ri = b[i] - y[i];
+    r[i] = ri;
+    rh[i] = ri;
+    p[i] = 0.0;
+    v[i] = 0.0;
+  }
+}
+
+// p = r + bt (p - om v)
+__global__ __launch_bounds__(256) void bicg_p_kernel(
+    const double* __restrict__ r, const double* __restrict__ v, double bt,
+    double om, int64_t N, double* __restrict__ p) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256)
+    p[i] = r[i] + bt * (p[i] - om * v[i]);
+}
+
+// s = r - al v
+__global__ __launch_bounds__(256) void bicg_s_kernel(
+    const double* __restrict__ r, const double* __restrict__ v, double al,
+    int64_t N, double* __restrict__ s) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256)
+    s[i] = r[i] - al * v[i];
+}
+
+// x += al p + om s;  r = s - om t   (om = 0: x += al p only)
+__global__ __launch_bounds__(256) void bicg_x_kernel(
+    const double* __restrict__ p, const double* __restrict__ s,
+    const double* __restrict__ t, double al, double om, int64_t N,
+    double* __restrict__ x, double* __restrict__ r) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * 256) {
+    x[i] += al * p[i] + om * s[i];
+    if (r) r[i] = s[i] - om * t[i];
+  }
+}
+
+}  // namespace
+
+size_t krylov_scratch_bytes(int64_t N) {
+  return (size_t)N * 7 * 8 + (size_t)kDotBlocks * 2 * 8 + 64;
+}
+
+orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
+                                  const int64_t* row_ptr, const int32_t* col,
+                                  const double* val, const uint8_t* row_kind,
+                                  double alpha, double beta, const double* b,
+                                  double* x, double tol, int max_iter,
+                                  int* iters, double* relres) {
+  orbf_status st = ORBF_OK;
+  auto* w = (double*)scratch(ctx, B_KRYLOV, krylov_scratch_bytes(N), &st);
+  if (st) return st;
+  double* r = w;
+  double* rh = r + N;
+  double* p = rh + N;
+  double* v = p + N;
+  double* s = v + N;
+  double* t = s + N;
+  double* y = t + N;
+  double* part = y + N;
+  double* out = part + 2 * kDotBlocks;
+  hipStream_t sm = ctx->stream;
+  const int64_t rows_blocks = (N + 15) / 16;
+  const unsigned ga = (unsigned)(rows_blocks < 65536 ? rows_blocks : 65536);
+  const int64_t vb = (N + 255) / 256;
+  const unsigned gv = (unsigned)(vb < 65536 ? vb : 65536);
+  const int gd = (int)(vb < kDotBlocks ? vb : kDotBlocks);
+  double* h = ctx->host_scalars;
+  auto apply = [&](const double* in, double* res) {
+    hipLaunchKernelGGL(apply_kernel, dim3(ga), dim3(256), 0, sm, row_ptr, col,
+                       val, row_kind, alpha, beta, in, N, res);
+  };
+  // (a.b, c.d) on the host
+  auto dots = [&](const double* a, const double* bb, const double* c,
+                  const double* d, double* o1, double* o2) -> orbf_status {
+    hipLaunchKernelGGL(dot2_kernel, dim3(gd), dim3(256), 0, sm, a, bb, c, d,
+                       N, part);
+    hipLaunchKernelGGL(dot2_final_kernel, dim3(1), dim3(64), 0, sm, part, gd,
+                       out);
+    hipError_t e = hipMemcpyAsync(h, out, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, sm);
+    if (e == hipSuccess) e = hipStreamSynchronize(sm);
+    if (e != hipSuccess) return hip_check(ctx, e, "solve: inner product");
+    *o1 = h[0];
+    if (o2) *o2 = h[1];
+    return ORBF_OK;
+  };
+
+  apply(x, y);
+  hipLaunchKernelGGL(bicg_init_kernel, dim3(gv), dim3(256), 0, sm, b, y, N,
+                     r, rh, p, v);
+  double bb = 0.0, rr = 0.0;
+  if ((st = dots(b, b, r, r, &bb, &rr))) return st;
+  const double nb = bb > 0.0 ? sqrt(bb) : 1.0;
+  double res = sqrt(rr) / nb;
+  int it = 0;
+  double rho = 1.0, al = 1.0, om = 1.0, rho_new = 0.0;
+  if ((st = dots(rh, r, nullptr, nullptr, &rho_new, nullptr))) return st;
+  while (res > tol && it < max_iter) {
+    if (rho_new == 0.0) break;  // breakdown: report the residual reached
+    ++it;
+    const double bt = (rho_new / rho) * (al / om);
+    hipLaunchKernelGGL(bicg_p_kernel, dim3(gv), dim3(256), 0, sm, r, v, bt,
+                       om, N, p);
+    apply(p, v);
+    double rhv = 0.0;
+    if ((st = dots(rh, v, nullptr, nullptr, &rhv, nullptr))) return st;
+    if (rhv == 0.0) break;
+    al = rho_new / rhv;
+    hipLaunchKernelGGL(bicg_s_kernel, dim3(gv), dim3(256), 0, sm, r, v, al, N,
+                       s);
+    double ss = 0.0;
+    if ((st = dots(s, s, nullptr, nullptr, &ss, nullptr))) return st;
+    if (sqrt(ss) / nb <= tol) {  // converged on the half step
+      hipLaunchKernelGGL(bicg_x_kernel, dim3(gv), dim3(256), 0, sm, p, s, t,
+                         al, 0.0, N, x, (double*)nullptr);
+      res = sqrt(ss) / nb;
+      break;
+    }
+    apply(s, t);
+    double ts = 0.0, tt = 0.0;
+    if ((st = dots(t, s, t, t, &ts, &tt))) return st;
+    if (tt == 0.0) break;
+    om = ts / tt;
+    hipLaunchKernelGGL(bicg_x_kernel, dim3(gv), dim3(256), 0, sm, p, s, t, al,
+                       om, N, x, r);
+    rho = rho_new;
+    if ((st = dots(rh, r, r, r, &rho_new, &rr))) return st;
+    res = sqrt(rr) / nb;
+    if (om == 0.0) break;
+  }
+  if (iters) *iters = it;
+  if (relres) *relres = res;
+  return hip_check(ctx, hipGetLastError(), "solve");
+}
+
+}  // namespace orbf

@@ -118,6 +118,7 @@ struct orbf_ctx {
   float phase_ms[5] = {0, 0, 0, 0, 0};
   bool phase_valid[5] = {false, false, false, false, false};
   int64_t* host_counter = nullptr;  // pinned, covering round control
+  double* host_scalars = nullptr;  // pinned, inner products of a solve
   // rounds over the covering's straggler list that each (xyz, knn, N)
   // needed in an eager call; a captured call replays that many
   std::vector<std::pair<const void*, int64_t>> cover_keys;
@@ -160,6 +161,7 @@ enum BufId {
   B_CLASS_N,
   B_P_CACHE,
   B_GERSH,
+  B_KRYLOV,
   B_NUM,
 };
 static_assert(B_NUM <= 32, "orbf_ctx::buf holds 32 scratch buffers");
@@ -193,6 +195,13 @@ orbf_status launch_gershgorin(orbf_ctx* ctx, int64_t N,
                               const int64_t* row_ptr, const int32_t* col,
                               const double* val, double* diag, double* radius,
                               double* summary);
+size_t krylov_scratch_bytes(int64_t N);
+orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
+                                  const int64_t* row_ptr, const int32_t* col,
+                                  const double* val, const uint8_t* row_kind,
+                                  double alpha, double beta, const double* b,
+                                  double* x, double tol, int max_iter,
+                                  int* iters, double* relres);
 orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        const int32_t* owner, const double* W,
                        int64_t* row_ptr, int32_t* col, double* val);
