@@ -126,6 +126,35 @@ def test_batched_graph_replay(orbf):
             same(o, r)
 
 
+def test_graph_replay_meets_a_deeper_covering(orbf):
+    """A replayed graph launches the number of covering levels recorded when
+    it was captured; one workgroup then runs whatever levels remain.  The
+    batch is captured on Halton-ordered nodes (a shallow dependency DAG),
+    then the same buffers are refilled with the nodes in lexicographic order
+    (a deep one) and the graph replayed: the result must equal an eager
+    build of the sorted nodes, and the oracle's covering."""
+    ctx = orbf.Context(0)
+    spec = dict(d=3, N=12000, n=50, m=5, l=3, delta=0.3)
+    x = nodesets.ball(spec["N"], 2)["x"]
+    xs = np.ascontiguousarray(x[np.lexsort((x[:, 2], x[:, 1], x[:, 0]))])
+    sets = [as_set(spec, x)]
+    outs = orbf.build_dm_batched(ctx, sets)
+    for _ in range(2):  # captured, then replayed
+        orbf.build_dm_batched(ctx, sets, outputs=outs)
+    sets[0]["xyz"].copy_(gpu(xs))
+    torch.cuda.synchronize()
+    _say("[gpu] graph replay on lexicographically ordered nodes")
+    orbf.build_dm_batched(ctx, sets, outputs=outs)
+    ref = orbf.build_dm(gpu(xs), spec["n"], spec["m"], spec["l"],
+                        spec["delta"], ctx=orbf.Context(0))
+    same(outs[0], ref)
+    idx, rho2 = oracle.knn(xs, spec["n"])
+    owner, centers = oracle.cover(xs, idx, rho2, spec["delta"])
+    assert np.array_equal(outs[0]["owner"].cpu().numpy(), owner)
+    assert np.array_equal(ref["centers"].cpu().numpy()[:len(centers)],
+                          centers)
+
+
 def test_batched_fp32_refined(orbf):
     ctx = orbf.Context(0)
     specs = small_specs(12, 9)

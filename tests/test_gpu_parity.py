@@ -54,6 +54,9 @@ CASES = {
     "square45_d02": dict(kind="square", n=12, m=3, l=2, delta=0.2),
     "disk5k_d05": dict(kind="disk", N=5000, n=31, m=5, l=4, delta=0.5),
     "ball20k_d03": dict(kind="ball", N=20000, n=50, m=5, l=3, delta=0.3),
+    # spatially sorted nodes: the covering's dependency DAG is deep
+    "ball20k_lex_d03": dict(kind="ball_lex", N=20000, n=50, m=5, l=3,
+                            delta=0.3),
     "ball1237_d0": dict(kind="ball", N=1237, n=20, m=3, l=2, delta=0.0),
     "disk5k_d03_tau1": dict(kind="disk", N=5000, n=31, m=5, l=4, delta=0.3,
                             tau=1.0),
@@ -82,6 +85,9 @@ def make(case):
         x, el, bnd, nrm = D["x"], D["eligible"], D["boundary"], D["normals"]
     else:
         x = nodesets.ball(c["N"], 2)["x"]
+        if c["kind"] == "ball_lex":
+            x = np.ascontiguousarray(
+                x[np.lexsort((x[:, 2], x[:, 1], x[:, 0]))])
     return x, el, bnd, nrm, c
 
 
@@ -321,7 +327,11 @@ def test_fp32_refined_ball_full_size(orbf, ctx):
                                   "square45_d1"])
 def test_workspace_size_bounds_scratch(orbf, case):
     """A context capped at orbf_workspace_size completes a build (either
-    precision, finite tau, boundary rows); half of it is refused."""
+    precision, finite tau, boundary rows); a cap below the kNN's own
+    scratch (its N n recorded squared distances plus the grid arrays) is
+    refused.  The size covers the Lebesgue covering's predecessor lists,
+    which a build with tau = inf does not allocate, so half of it can
+    suffice there."""
     x, el, bnd, nrm, c = make(case)
     tau = c.get("tau", math.inf)
     for prec in (orbf.PREC_FP64, orbf.PREC_FP32_IR):
@@ -332,9 +342,10 @@ def test_workspace_size_bounds_scratch(orbf, case):
                   normals=None if nrm is None else gpu(nrm), prec=prec)
         orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"],
                       ctx=orbf.Context(0, budget=ws), **kw)
+        small = min(ws // 2, len(x) * c["n"] * 8)
         with pytest.raises(orbf.OrbfError) as e:
             orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"],
-                          ctx=orbf.Context(0, budget=ws // 2), **kw)
+                          ctx=orbf.Context(0, budget=small), **kw)
         assert e.value.code == orbf.EBUDGET
 
 
