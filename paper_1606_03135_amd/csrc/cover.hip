@@ -164,16 +164,24 @@ __global__ __launch_bounds__(256) void ball_d2_quad_kernel(
 //
 // Sixteen lanes process a node, one stencil position each (eight passes for
 // n <= 128), so its successors' atomics are in flight together.  The group
-// keeps up to kFollow of the nodes it decides on a small LDS stack and
-// processes them in the same launch, which shortens the long index-local
-// chains of spatially ordered inputs; the rest go to the next level's
-// queue.
+// keeps some of the nodes it decides on a small LDS stack and processes them
+// in the same launch; the rest go to the next level's queue.  Following
+// many saves levels while the frontier is wide (the first levels of a
+// scattered numbering); on the deep, narrow DAGs of spatially ordered
+// inputs it only serialises atomics, so later levels follow one.
 constexpr int kStack = 16;     // LDS stack entries per group
-// Measured on the 1M-node ball (covering phase, ms; Halton / Morton /
-// lexicographic node order): following 0 nodes 1.88 / 3.92 / 4.55,
-// 16 nodes 1.09 / 5.14 / 7.15 (sweeps over the undecided nodes instead:
-// 1.04 / 20.1 / 21.8); 256 blocks instead of 1024 are slower throughout.
-constexpr int kFollow = 16;    // nodes a group follows per queue entry
+// Measured, covering phase in ms: 1M-node ball in Halton / Morton /
+// lexicographic order; 2D raster grids of 20k and 200k nodes at delta 0.3;
+// the 512-set batch in FP64 weights/s:
+//   sweeps over undecided nodes     1.04 / 20.1 / 21.7; 1.58 / 8.94; 7.15e8
+//   follow 16 at every level        1.08 /  5.1 /  7.2; 2.54 / 8.64; 6.70e8
+//   follow 4 at every level         1.39 /  5.4 /  6.0; 1.72 / 5.40; 7.50e8
+//   follow 16 for 4 levels, then 1  1.09 /  3.7 /  4.1; 1.15 / 3.48; 7.99e8
+// (then 0: 1.14 / 4.3 / 4.7; then 2: 1.08 / 3.8 / 4.5; 256 or fewer blocks
+// per level: slower on deep DAGs).
+constexpr int kFollowWide = 16;  // nodes followed per entry, first levels
+constexpr int kFollowDeep = 1;   // nodes followed per entry, later levels
+constexpr int kWideLevels = 4;
 constexpr int kLevelBlocks = 1024;
 constexpr int32_t kCenterBit = INT32_MIN;  // stack/queue entry: center flag
 
@@ -208,11 +216,11 @@ __device__ __forceinline__ void process_entry(
     int32_t entry, int32_t* stk, const int32_t* __restrict__ knn,
     const uint64_t* __restrict__ ball, int n, int32_t* cnt, int32_t* state,
     int32_t* owner, int32_t* __restrict__ is_center,
-    int32_t* __restrict__ qnext, int32_t* qn) {
+    int32_t* __restrict__ qnext, int32_t* qn, int follow) {
   const int lane = (int)(threadIdx.x & 63), pl = lane & 15;
   const int gshift = lane & 48;  // first lane of the group in the wave
   const uint32_t below = (1u << pl) - 1u;
-  int sp = 0, follow = kFollow;
+  int sp = 0;
   int32_t e = entry;
   for (;;) {
     const int32_t c = e & INT32_MAX;
@@ -278,7 +286,7 @@ __global__ __launch_bounds__(256) void level_kernel(
     const int32_t* __restrict__ knn, const uint64_t* __restrict__ ball,
     int n, int32_t* cnt, int32_t* state, int32_t* owner,
     int32_t* __restrict__ is_center, int32_t* __restrict__ q0,
-    int32_t* __restrict__ q1, int32_t* qc, int lv) {
+    int32_t* __restrict__ q1, int32_t* qc, int lv, int follow) {
   __shared__ int32_t stk[16 * kStack];
   const int32_t count = qc[lv % 3];
   if (blockIdx.x == 0 && threadIdx.x == 0) qc[(lv + 2) % 3] = 0;
@@ -289,7 +297,7 @@ __global__ __launch_bounds__(256) void level_kernel(
   for (int64_t t = (int64_t)blockIdx.x * 16 + grp; t < count;
        t += (int64_t)gridDim.x * 16)
     process_entry(cur[t], stk + grp * kStack, knn, ball, n, cnt, state,
-                  owner, is_center, nxt, qn);
+                  owner, is_center, nxt, qn, follow);
 }
 
 // One workgroup runs the remaining levels from `lv` until a queue is empty.
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(256) void finish_levels_kernel(
     int32_t* nxt = (lv & 1) ? q0 : q1;
     for (int t = grp; t < count; t += 16)
       process_entry(cur[t], stk + grp * kStack, knn, ball, n, cnt, state,
-                    owner, is_center, nxt, &qc[(lv + 1) % 3]);
+                    owner, is_center, nxt, &qc[(lv + 1) % 3], kFollowDeep);
     __threadfence();
   }
 }
@@ -405,8 +413,9 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   int lv = 0;
   auto levels = [&](int k) {
     for (int r = 0; r < k; ++r, ++lv)
-      hipLaunchKernelGGL(level_kernel, dim3(gl), dim3(256), 0, s, knn, ball, n,
-                         cnt, state, owner, flag, q0, q1, qc, lv);
+      hipLaunchKernelGGL(level_kernel, dim3(gl), dim3(256), 0, s, knn, ball,
+                         n, cnt, state, owner, flag, q0, q1, qc, lv,
+                         lv < kWideLevels ? kFollowWide : kFollowDeep);
   };
   // The number of levels is the depth of the DAG left after the threads'
   // own chain following, known only on the device.  An eager call launches
