@@ -277,6 +277,15 @@ __device__ __forceinline__ int cell_coord(double v, const GridParams& g,
   return c >= g.nc[a] ? g.nc[a] - 1 : c;
 }
 
+// Cell index of coordinate v on axis a, clamped to the grid, for any finite
+// v (the same truncation as cell_coord, so a node whose coordinate lies in
+// [u, w] has its cell in [box_cell(u), box_cell(w)]).
+__device__ __forceinline__ int box_cell(double v, const GridParams& g, int a) {
+  double t = (v - g.lo[a]) * g.inv_s;
+  t = fmin(fmax(t, 0.0), (double)(g.nc[a] - 1));
+  return (int)t;
+}
+
 __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t n,
                                                         int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
@@ -312,14 +321,18 @@ __global__ __launch_bounds__(256) void cell_scatter_kernel(
   }
 }
 
-// One wavefront per query.  Candidates with d^2 < T are compacted into LDS
-// in one pass and ordered exactly by (d^2, index) with an in-register
+// One wavefront per query.  The scanned block is the box of cells around the
+// ball of the expected stencil radius (the previous query's, x sqrt(kGrow)),
+// so most queries prove their stencil in the first block (rings of whole
+// cells around the query's own cell, 3^d and then 5^d: 3.01 ms against
+// 2.89 ms on the 1M-node ball).  Candidates with d^2 < T are compacted into
+// LDS in one pass and ordered exactly by (d^2, index) with an in-register
 // bitonic sort (64 or 128 keys); T starts from the previous query's n-th
 // distance (queries run in cell order, so neighbours have nearly the same
 // stencil radius) and is corrected by bisection when the pass keeps fewer
-// than n or more than 128 candidates.  T never exceeds
-// the squared distance to the boundary of the scanned block, so the result
-// is exact: every node outside the block is farther than every kept one.
+// than n or more than 128 candidates.  T never exceeds the squared distance
+// to the boundary of the scanned block, so the result is exact: every node
+// outside the block is farther than every kept one.
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
     const double* __restrict__ xs, const int32_t* __restrict__ perm,
@@ -340,25 +353,27 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
     const int32_t qi = perm[qs];
     const double q0 = xs[qs * d], q1 = xs[qs * d + 1];
     const double q2 = (d == 3) ? xs[qs * d + 2] : 0.0;
-    const int cq0 = cell_coord(q0, g, 0), cq1 = cell_coord(q1, g, 1);
-    const int cq2 = (d == 3) ? cell_coord(q2, g, 2) : 0;
     bool dup = false;
     bool done = false;
 
-    for (int R = 1; !done; ++R) {
-      const int lo0 = max(cq0 - R, 0), hi0 = min(cq0 + R, g.nc[0] - 1);
-      const int lo1 = max(cq1 - R, 0), hi1 = min(cq1 + R, g.nc[1] - 1);
-      const int lo2 = (d == 3) ? max(cq2 - R, 0) : 0;
-      const int hi2 = (d == 3) ? min(cq2 + R, g.nc[2] - 1) : 0;
+    // the block of cells that holds the ball of radius `rad` around the
+    // query; rad starts from the expected stencil radius and grows by 1.5x
+    // while the block cannot prove n neighbours
+    double rad = sqrt(est > 0.0 ? est * kGrow : g.s * g.s);
+    for (int grow = 0; !done && grow < 64; ++grow, rad *= 1.5) {
+      const int lo0 = box_cell(q0 - rad, g, 0), hi0 = box_cell(q0 + rad, g, 0);
+      const int lo1 = box_cell(q1 - rad, g, 1), hi1 = box_cell(q1 + rad, g, 1);
+      const int lo2 = (d == 3) ? box_cell(q2 - rad, g, 2) : 0;
+      const int hi2 = (d == 3) ? box_cell(q2 + rad, g, 2) : 0;
       bool whole = true;
       double b = INFINITY;
-      if (cq0 - R > 0) { b = fmin(b, q0 - (g.lo[0] + (double)(cq0 - R) * g.s)); whole = false; }
-      if (cq0 + R < g.nc[0] - 1) { b = fmin(b, (g.lo[0] + (double)(cq0 + R + 1) * g.s) - q0); whole = false; }
-      if (cq1 - R > 0) { b = fmin(b, q1 - (g.lo[1] + (double)(cq1 - R) * g.s)); whole = false; }
-      if (cq1 + R < g.nc[1] - 1) { b = fmin(b, (g.lo[1] + (double)(cq1 + R + 1) * g.s) - q1); whole = false; }
+      if (lo0 > 0) { b = fmin(b, q0 - (g.lo[0] + (double)lo0 * g.s)); whole = false; }
+      if (hi0 < g.nc[0] - 1) { b = fmin(b, (g.lo[0] + (double)(hi0 + 1) * g.s) - q0); whole = false; }
+      if (lo1 > 0) { b = fmin(b, q1 - (g.lo[1] + (double)lo1 * g.s)); whole = false; }
+      if (hi1 < g.nc[1] - 1) { b = fmin(b, (g.lo[1] + (double)(hi1 + 1) * g.s) - q1); whole = false; }
       if (d == 3) {
-        if (cq2 - R > 0) { b = fmin(b, q2 - (g.lo[2] + (double)(cq2 - R) * g.s)); whole = false; }
-        if (cq2 + R < g.nc[2] - 1) { b = fmin(b, (g.lo[2] + (double)(cq2 + R + 1) * g.s) - q2); whole = false; }
+        if (lo2 > 0) { b = fmin(b, q2 - (g.lo[2] + (double)lo2 * g.s)); whole = false; }
+        if (hi2 < g.nc[2] - 1) { b = fmin(b, (g.lo[2] + (double)(hi2 + 1) * g.s) - q2); whole = false; }
       }
       // unscanned nodes are at least b away; the margin absorbs rounding in
       // d^2, in b and in the cell assignment
@@ -467,6 +482,7 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
         break;
       }
     }
+    if (!done && lane == 0) report(st, ORBF_EINTERNAL, qi);
     if (__ballot(dup) && lane == 0) report(st, ORBF_EDUPLICATE, qi);
   }
 }
