@@ -9,6 +9,9 @@ every node, FP64.  Prints one JSON line: weights/s (nnz / build time),
 stencils/s, phase times, p50/p99 build latency, the FP64 roofline fraction
 of the weights kernel, the FP32 + FP64-refinement variant of the same build
 with its weight error, and the CPU oracle's rate on the same workload.
+After the timed builds, the built DM's consumers are timed on their own:
+its Gershgorin disks, y = L x, and one backward-Euler step (I - dt L) u1 =
+u0 with Dirichlet rows on the sphere, solved by BiCGSTAB.
 
 --workload batched: 512 mixed node sets (N log-uniform in [1e3, 2e5], 2D/3D,
 l in {2,3,4}, n in [2M+1, 3M], delta in {0.2, 0.5, 1}) in one batched call,
