@@ -133,7 +133,7 @@ orbf_status orbf_build_nodes_knn(orbf_ctx* ctx, const double* xyz, int64_t N,
  * (retention distance (1-delta) rho_k; delta = 1 gives standard RBF-FD with
  * every eligible node its own center, delta = 0 keeps the whole stencil).
  * The result is the sequential greedy result exactly, although the device
- * evaluates it in parallel rounds.
+ * evaluates it in parallel: each decided node updates its successors once.
  *   eligible  : N uint8 (nonzero = gets an interior row) or NULL for all
  *   centers   : capacity N int32 output, centers in ascending order
  *   n_centers : 1 int64 output (device): number of centers N_delta
