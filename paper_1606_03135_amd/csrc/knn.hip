@@ -393,15 +393,21 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
         const int ny = hi1 - lo1 + 1;
         const int rows = ny * (hi2 - lo2 + 1);
         const int half = lane >> 5, hl = lane & 31;
+        // (y, z) of this half's row, advanced by two rows per step without
+        // a division (ny >= 1, so two wraps at most)
+        int y = lo1 + half, z = lo2;
+        if (y > hi1) { y -= ny; ++z; }
         for (int pr = 0; pr < rows; pr += 2) {
           const int row = pr + half;
           int64_t s0 = 0, s1 = 0;
           if (row < rows) {
-            const int z = lo2 + row / ny, y = lo1 + row % ny;
             const int64_t crow = ((int64_t)z * g.nc[1] + y) * g.nc[0];
             s0 = cstart[crow + lo0];
             s1 = cstart[crow + hi0 + 1];
           }
+          y += 2;
+          if (y > hi1) { y -= ny; ++z; }
+          if (y > hi1) { y -= ny; ++z; }
           for (int64_t t = s0 + hl; __ballot(t < s1) != 0ull; t += 32) {
             bool keep = false;
             double d2 = 0.0;
