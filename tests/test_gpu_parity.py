@@ -155,6 +155,46 @@ def test_disk_full_size(orbf, ctx):
     assert err <= TOL
 
 
+def _morton(x, bits=10):
+    """Morton (Z-order) permutation of points in [-1, 1]^3."""
+    q = np.clip(((x + 1) / 2 * (1 << bits)).astype(np.int64), 0,
+                (1 << bits) - 1)
+    code = np.zeros(len(x), np.int64)
+    for b in range(bits):
+        for a in range(x.shape[1]):
+            code |= ((q[:, a] >> b) & 1) << (x.shape[1] * b + a)
+    return np.argsort(code, kind="stable")
+
+
+def test_cover_full_size_morton_order(orbf, ctx):
+    """The 1M-node ball numbered in Morton order (a covering DAG about 360
+    levels deep, against about 40 for the Halton numbering): stencils and
+    the whole covering bit for bit against the oracle, on the first call
+    and again on a repeated call that starts from the recorded level
+    count."""
+    x = nodesets.ball(1000000, 2)["x"]
+    x = np.ascontiguousarray(x[_morton(x)])
+    _say(f"[gpu] Morton-ordered ball N={len(x)}: kNN and covering")
+    idx, rho2 = oracle.knn(x, 50, method="grid")
+    owner_ref, centers_ref = oracle.cover(x, idx, rho2, 0.3)
+    xd = gpu(x)
+    k, r = orbf.build_nodes_knn(ctx, xd, 50)
+    assert np.array_equal(k.cpu().numpy(), idx)
+    assert np.array_equal(r.cpu().numpy(), rho2)
+    for call in range(2):
+        centers, nc, owner, p = orbf.select_overlapped_stencils(
+            ctx, xd, k, r, 0.3)
+        ctx.sync()
+        nc = int(nc.item())
+        _say(f"[gpu] Morton-ordered ball, call {call}: N_delta={nc}")
+        assert np.array_equal(owner.cpu().numpy(), owner_ref)
+        assert np.array_equal(centers.cpu().numpy()[:nc], centers_ref)
+        assert np.array_equal(
+            p.cpu().numpy()[:nc],
+            np.bincount(owner_ref[owner_ref >= 0],
+                        minlength=len(x))[centers_ref])
+
+
 def test_ball_full_size_sampled(orbf, ctx):
     """3D ball, N = 1,000,000, n = 50, l = 3, r^5, delta = 0.3: stencils of
     sampled nodes by brute force, the covering in full (oracle grid kNN +
