@@ -283,6 +283,35 @@ orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
                                 double* x, double tol, int max_iter,
                                 int* iters, double* relres);
 
+/* Coefficients of the backward differentiation formula of order k = 1..4
+ * (Sec. 5 time-steps with BDF4 and starts it with BDF1-3):
+ *     u^{n+1} - sum_{i<k} a[i] u^{n-i} = b dt F(u^{n+1}),
+ * k = 4: a = (48, -36, 16, -3)/25, b = 12/25.  a: 4 host doubles (zero
+ * past k), b: 1 host double.  Needs no context.  Errors: EINVAL. */
+orbf_status orbf_bdf_coefficients(int order, double* a, double* b);
+
+/* Right-hand side of one BDF step of u_t = nu L u + f with the DM (Sec. 5):
+ *     rhs_e = sum_{i<k} a[i] u_i[e] + b dt f[e]   where row_kind[e] == 1
+ *     rhs_e = bvals[e] (0 if bvals is NULL)        elsewhere
+ * with a, b from orbf_bdf_coefficients.  Solving
+ * orbf_solve_implicit(..., row_kind, 1, -b nu dt, rhs, x, ...) then gives
+ * u^{n+1}: interior rows satisfy the BDF formula, Dirichlet rows take
+ * bvals, boundary-operator rows (e.g. Neumann) equal bvals.
+ *   order    : k = 1..4
+ *   u0..u3   : N FP64 (device): u0 = u^n (newest), u1 = u^{n-1}, ...; the
+ *              first k must be non-NULL, the rest are ignored
+ *   f        : N FP64 forcing at t^{n+1} (device), or NULL for none
+ *   row_kind : N bytes (device), as for orbf_solve_implicit, or NULL
+ *   bvals    : N FP64 boundary data at t^{n+1} (device), or NULL
+ *   rhs      : N FP64 output (device), must not alias a time level
+ * Errors: EINVAL (N out of range, order, NULL level or rhs, aliasing,
+ * dt not finite and positive). */
+orbf_status orbf_bdf_rhs(orbf_ctx* ctx, int64_t N, int order,
+                         const double* u0, const double* u1,
+                         const double* u2, const double* u3, const double* f,
+                         double dt, const uint8_t* row_kind,
+                         const double* bvals, double* rhs);
+
 /* Kernel schedules for the weights.  Stencils of one system size K = n + M
  * are solved by one of these kernels; which is fastest depends on K and on
  * how many rows a stencil keeps, estimated as n (1-delta)^d: p-class 0 for

@@ -302,6 +302,51 @@ def solve_implicit(row_ptr, col, val, b, row_kind=None, alpha=1.0,
     return spl.spsolve(A.tocsc(), np.asarray(b, dtype=float))
 
 
+def bdf_coefficients(k):
+    """Backward differentiation formula of order k (Sec. 5 steps with BDF4
+    and starts with BDF1-3): u^{n+1} - sum_i a_i u^{n-i} = b dt u'(t^{n+1}).
+    From its definition: exact for every polynomial of degree <= k in t on
+    equal steps.  With s = (t - t^{n+1}) / dt the nodes are s = 0, -1, ...,
+    -k and the conditions on s^j, j = 0..k, form a (k+1) x (k+1) linear
+    system in (a_0..a_{k-1}, b).  Returns (a, b), a of length k."""
+    # sum_i a_i (-(i+1))^j + b * [j == 1] = 0^j   (0^0 = 1)
+    A = np.zeros((k + 1, k + 1))
+    rhs = np.zeros(k + 1)
+    for j in range(k + 1):
+        for i in range(k):
+            A[j, i] = float(-(i + 1)) ** j
+        A[j, k] = 1.0 if j == 1 else 0.0
+        rhs[j] = 1.0 if j == 0 else 0.0
+    sol = np.linalg.solve(A, rhs)
+    return sol[:k], float(sol[k])
+
+
+def bdf_rhs(levels, dt, f=None, row_kind=None, bvals=None):
+    """Right-hand side of one BDF step of u_t = nu L u + f (Sec. 5):
+    sum_i a_i u^{n-i} + b dt f on interior rows (row_kind 1, or all rows if
+    row_kind is None), the boundary value (or 0) elsewhere; ``levels`` =
+    [u^n, u^{n-1}, ...], newest first, its length the order."""
+    a, b = bdf_coefficients(len(levels))
+    out = np.zeros_like(np.asarray(levels[0], dtype=float))
+    for ai, u in zip(a, levels):
+        out = out + ai * np.asarray(u, dtype=float)
+    if f is not None:
+        out = out + b * dt * np.asarray(f, dtype=float)
+    if row_kind is not None:
+        other = np.asarray(row_kind) != 1
+        out[other] = 0.0 if bvals is None else np.asarray(bvals)[other]
+    return out
+
+
+def bdf_step(row_ptr, col, val, levels, dt, nu=1.0, f=None, row_kind=None,
+             bvals=None):
+    """u^{n+1} of one BDF step (Sec. 5): the implicit system with alpha = 1,
+    beta = -b nu dt and the right-hand side of ``bdf_rhs``."""
+    _, b = bdf_coefficients(len(levels))
+    rhs = bdf_rhs(levels, dt, f, row_kind, bvals)
+    return solve_implicit(row_ptr, col, val, rhs, row_kind, 1.0, -b * nu * dt)
+
+
 def build_dm(x, n, m, l, delta, tau=np.inf, eligible=None, boundary=None,
              normals=None, nthreads=0, knn_method="auto", op=OP_LAPLACIAN):
     """Whole oracle pipeline: stencils, covering (+Lebesgue), interior rows

@@ -117,6 +117,12 @@ def lib():
             _P, _I64, _P, _P, _P, _P, _D, _D, _P, _P, _D, _I,
             ctypes.POINTER(_I), ctypes.POINTER(_D)]
         L.orbf_solve_implicit.restype = _I
+        L.orbf_bdf_coefficients.argtypes = [_I, ctypes.POINTER(_D),
+                                             ctypes.POINTER(_D)]
+        L.orbf_bdf_coefficients.restype = _I
+        L.orbf_bdf_rhs.argtypes = [_P, _I64, _I, _P, _P, _P, _P, _P, _D, _P,
+                                   _P, _P]
+        L.orbf_bdf_rhs.restype = _I
         L.orbf_phase_times.argtypes = [_P, ctypes.POINTER(_D)]
         L.orbf_phase_times.restype = _I
         L.orbf_build_dm_batched.argtypes = [_P, ctypes.POINTER(SetDesc), _I]
@@ -369,6 +375,47 @@ def solve_implicit(ctx, row_ptr, col, val, b, *, alpha=1.0, beta=-1.0,
         float(alpha), float(beta), _ptr(b), _ptr(x), float(tol),
         int(max_iter), ctypes.byref(it), ctypes.byref(res)))
     return x, it.value, res.value
+
+
+def bdf_coefficients(order):
+    """(a[0..3], b) of the BDF of ``order`` 1..4 (Sec. 5):
+    u^{n+1} - sum_i a[i] u^{n-i} = b dt F(u^{n+1})."""
+    a = (_D * 4)()
+    b = _D(0.0)
+    if lib().orbf_bdf_coefficients(int(order), a, ctypes.byref(b)) != OK:
+        raise ValueError("BDF order must be 1..4")
+    return list(a), b.value
+
+
+def bdf_step(ctx, row_ptr, col, val, levels, dt, *, nu=1.0, f=None,
+             row_kind=None, bvals=None, tol=1e-12, max_iter=1000):
+    """One BDF step of u_t = nu L u + f with the DM (Sec. 5), of order
+    len(levels) (1..4; ``levels`` = [u^n, u^{n-1}, ...], newest first):
+    orbf_bdf_rhs, then orbf_solve_implicit from u^n.  Returns (u^{n+1},
+    iterations, relative residual)."""
+    k = len(levels)
+    if not 1 <= k <= 4:
+        raise ValueError("BDF order must be 1..4")
+    levels = [_dev(u, torch.float64, "u") for u in levels]
+    N = levels[0].numel()
+    if f is not None:
+        f = _dev(f, torch.float64, "f")
+    if row_kind is not None:
+        row_kind = _dev(row_kind, torch.uint8, "row_kind")
+    if bvals is not None:
+        bvals = _dev(bvals, torch.float64, "bvals")
+    for t in [f, row_kind, bvals] + levels:
+        if t is not None and t.numel() != N:
+            raise ValueError("every vector needs one entry per DM row")
+    rhs = torch.empty_like(levels[0])
+    u = levels + [None] * (4 - k)
+    ctx.check(lib().orbf_bdf_rhs(ctx._h, N, k, _ptr(u[0]), _ptr(u[1]),
+                                 _ptr(u[2]), _ptr(u[3]), _ptr(f), float(dt),
+                                 _ptr(row_kind), _ptr(bvals), _ptr(rhs)))
+    _, b = bdf_coefficients(k)
+    return solve_implicit(ctx, row_ptr, col, val, rhs, alpha=1.0,
+                          beta=-b * nu * dt, row_kind=row_kind, x0=levels[0],
+                          tol=tol, max_iter=max_iter)
 
 
 def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,

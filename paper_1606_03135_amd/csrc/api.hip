@@ -376,6 +376,33 @@ orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
                                beta, b, x, tol, max_iter, iters, relres);
 }
 
+orbf_status orbf_bdf_coefficients(int order, double* a, double* b) {
+  if (order < 1 || order > 4 || !a || !b) return ORBF_EINVAL;
+  bdf_coefficients(order, a, b);
+  return ORBF_OK;
+}
+
+orbf_status orbf_bdf_rhs(orbf_ctx* ctx, int64_t N, int order,
+                         const double* u0, const double* u1,
+                         const double* u2, const double* u3, const double* f,
+                         double dt, const uint8_t* row_kind,
+                         const double* bvals, double* rhs) {
+  if (!ctx) return ORBF_EINVAL;
+  if (N < 1 || N > INT32_MAX) return fail(ctx, ORBF_EINVAL, "N out of range");
+  if (order < 1 || order > 4)
+    return fail(ctx, ORBF_EINVAL, "BDF order must be 1..4");
+  const double* u[4] = {u0, u1, u2, u3};
+  for (int i = 0; i < order; ++i)
+    if (!u[i]) return fail(ctx, ORBF_EINVAL, "NULL time level");
+  if (!rhs) return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  for (int i = 0; i < order; ++i)
+    if (u[i] == rhs) return fail(ctx, ORBF_EINVAL, "rhs aliases a time level");
+  if (!isfinite(dt) || dt <= 0.0)
+    return fail(ctx, ORBF_EINVAL, "dt must be finite and positive");
+  hipSetDevice(ctx->device);
+  return launch_bdf_rhs(ctx, N, order, u, f, dt, row_kind, bvals, rhs);
+}
+
 orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,
                               orbf_schedule schedule) {
   if (!ctx) return ORBF_EINVAL;

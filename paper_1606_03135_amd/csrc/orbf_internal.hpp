@@ -196,6 +196,11 @@ orbf_status launch_gershgorin(orbf_ctx* ctx, int64_t N,
                               const double* val, double* diag, double* radius,
                               double* summary);
 size_t krylov_scratch_bytes(int64_t N);
+void bdf_coefficients(int k, double a[4], double* b);
+orbf_status launch_bdf_rhs(orbf_ctx* ctx, int64_t N, int k,
+                           const double* const u[4], const double* f,
+                           double dt, const uint8_t* row_kind,
+                           const double* bvals, double* rhs);
 orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
                                   const int64_t* row_ptr, const int32_t* col,
                                   const double* val, const uint8_t* row_kind,

@@ -94,3 +94,56 @@ def test_all_interior_default():
     got = oracle.solve_implicit(rp, col, val, u, None, 1.5, -1e-4)
     want = u / (1.5 - 1e-4 * lam)
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+# BDF time stepping (Sec. 5: BDF4, started with BDF1-3).
+
+def test_bdf4_coefficients_match_the_paper():
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "bdf4_coefficients.json")))
+    a, b = oracle.bdf_coefficients(g["order"])
+    want = np.array(g["a_num"], dtype=float) / g["den"]
+    assert np.abs(a - want).max() <= 1e-14
+    assert abs(b - g["b_num"] / g["den"]) <= 1e-14
+
+
+def test_bdf1_is_backward_euler_and_bdf2_textbook():
+    a, b = oracle.bdf_coefficients(1)
+    assert np.allclose(a, [1.0], rtol=0, atol=1e-15) and abs(b - 1.0) < 1e-15
+    a, b = oracle.bdf_coefficients(2)
+    assert np.allclose(a, [4 / 3, -1 / 3], rtol=0, atol=1e-15)
+    assert abs(b - 2 / 3) < 1e-15
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_bdf_order_of_accuracy_on_scalar_ode(k):
+    """u' = lam u through bdf_step on a one-node 'DM' L = [lam], from exact
+    history: the error at t = 1 falls like dt^k."""
+    lam = -1.3
+    rp, col = np.array([0, 1], np.int64), np.array([0], np.int32)
+    val = np.array([lam])
+    errs = []
+    for dt in (0.02, 0.01):
+        steps = int(round(1.0 / dt))
+        hist = [np.array([np.exp(lam * (-i) * dt)]) for i in range(k)]
+        # hist[i] = u(t = -i dt): newest first at t = 0
+        for s in range(steps):
+            un = oracle.bdf_step(rp, col, val, hist, dt)
+            hist = [un] + hist[:k - 1]
+        errs.append(abs(hist[0][0] - np.exp(lam)))
+    order = np.log2(errs[0] / errs[1])
+    assert abs(order - k) < 0.25, (k, errs, order)
+
+
+def test_bdf_rhs_boundary_rows():
+    u0 = np.array([1.0, 2.0, 3.0])
+    u1 = np.array([0.5, 0.5, 0.5])
+    kind = np.array([1, 0, 2], np.uint8)
+    bv = np.array([9.0, 7.0, -4.0])
+    out = oracle.bdf_rhs([u0, u1], 0.1, f=np.ones(3), row_kind=kind, bvals=bv)
+    assert out[0] == pytest.approx(4 / 3 * 1.0 - 1 / 3 * 0.5 + 2 / 3 * 0.1)
+    assert out[1] == 7.0 and out[2] == -4.0
+    out = oracle.bdf_rhs([u0, u1], 0.1, row_kind=kind)
+    assert out[1] == 0.0 and out[2] == 0.0
