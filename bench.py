@@ -10,8 +10,9 @@ stencils/s, phase times, p50/p99 build latency, the FP64 roofline fraction
 of the weights kernel, the FP32 + FP64-refinement variant of the same build
 with its weight error, and the CPU oracle's rate on the same workload.
 After the timed builds, the built DM's consumers are timed on their own:
-its Gershgorin disks, y = L x, and one backward-Euler step (I - dt L) u1 =
-u0 with Dirichlet rows on the sphere, solved by BiCGSTAB.
+its Gershgorin disks, y = L x, one backward-Euler step (I - dt L) u1 = u0
+with Dirichlet rows on the sphere, solved by BiCGSTAB, and BDF4 steps of
+the same problem (after one step each of BDF1-3).
 
 --workload batched: 512 mixed node sets (N log-uniform in [1e3, 2e5], 2D/3D,
 l in {2,3,4}, n in [2M+1, 3M], delta in {0.2, 0.5, 1}) in one batched call,
@@ -249,6 +250,25 @@ def bench_ball(args, torch, orbf, nodesets):
                             "ms_per_iteration": ims / max(its, 1),
                             "dt": 1e-5, "tol": 1e-10,
                             "dirichlet_rows": int(N - kind.sum().item())}
+    # BDF4 time stepping with the same DM and boundary (Sec. 5): one step
+    # each of BDF1-3, then BDF4 steps; the timed steps are BDF4
+    hist = [u0]
+    for _ in range(3):
+        un, _, _ = orbf.bdf_step(ctx, r["row_ptr"], r["col"], r["val"], hist,
+                                 1e-5, row_kind=kind, tol=1e-10)
+        hist = [un] + hist[:3]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bits = 0
+    for _ in range(5):
+        un, it, _ = orbf.bdf_step(ctx, r["row_ptr"], r["col"], r["val"], hist,
+                                  1e-5, row_kind=kind, tol=1e-10)
+        hist = [un] + hist[:3]
+        bits += it
+    torch.cuda.synchronize()
+    bms = 1e3 * (time.perf_counter() - t0) / 5
+    out["bdf4_step"] = {"ms": bms, "iterations_mean": bits / 5, "dt": 1e-5,
+                        "tol": 1e-10}
     if not args.no_fp32:
         W64 = r["W"].clone()
         steps32 = max(3, args.steps // 5)
