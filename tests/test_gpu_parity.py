@@ -57,6 +57,13 @@ CASES = {
     # spatially sorted nodes: the covering's dependency DAG is deep
     "ball20k_lex_d03": dict(kind="ball_lex", N=20000, n=50, m=5, l=3,
                             delta=0.3),
+    # delta-free retention (the follow-up the paper proposes): the whole
+    # stencil is the candidate set and the local Lebesgue test alone
+    # decides which rows a stencil keeps; tau = 1 is the paper's condition
+    "disk5k_d0_tau1": dict(kind="disk", N=5000, n=31, m=5, l=4, delta=0.0,
+                           tau=1.0),
+    "ball20k_d0_tau2": dict(kind="ball", N=20000, n=50, m=5, l=3, delta=0.0,
+                            tau=2.0),
     "ball1237_d0": dict(kind="ball", N=1237, n=20, m=3, l=2, delta=0.0),
     "disk5k_d03_tau1": dict(kind="disk", N=5000, n=31, m=5, l=4, delta=0.3,
                             tau=1.0),
