@@ -91,10 +91,15 @@ def _poisson_disk(R0, r, seed, ntries=30):
 _PD_FRACTION = 0.78
 
 
-def disk(n_int=99400, n_bnd=600, seed=1, order="shuffled"):
+def disk(n_int=99400, n_bnd=600, seed=1, order="shuffled", refine=False):
     """Unit disk: ``n_int`` interior Poisson-disk nodes (Bridson, 30 tries,
     PCG64(seed)) inside |x| <= 1 - h_b/2 with h_b = 2*pi/n_bnd, followed by
     ``n_bnd`` boundary nodes (cos 2*pi*b/n_bnd, sin 2*pi*b/n_bnd).
+
+    ``refine``: boundary refinement (Sec. 6, the node sets of Sec. 7): the
+    Poisson-disk interior stops at |x| <= 1 - h_b, and a copy of every
+    boundary node moved h_b/2 along the inward normal is appended to the
+    interior (eligible), so the interior then holds n_int + n_bnd nodes.
 
     A Poisson-disk run gives slightly more than n_int points; the surplus is
     removed at random (same stream family, seed+1000) so that no region is
@@ -104,7 +109,7 @@ def disk(n_int=99400, n_bnd=600, seed=1, order="shuffled"):
     Returns dict(x, n_int, n_bnd, eligible (uint8: interior), boundary
     (indices), normals (exact outward unit normals of the boundary nodes))."""
     h_b = 2.0 * math.pi / n_bnd
-    R0 = 1.0 - 0.5 * h_b
+    R0 = 1.0 - (1.0 if refine else 0.5) * h_b
     area = math.pi * R0 * R0
     frac = _PD_FRACTION
     for _ in range(8):
@@ -126,11 +131,14 @@ def disk(n_int=99400, n_bnd=600, seed=1, order="shuffled"):
         raise ValueError(order)
     th = 2.0 * math.pi * np.arange(n_bnd) / n_bnd
     bnd = np.stack([np.cos(th), np.sin(th)], axis=1)
+    if refine:
+        pts = np.concatenate([pts, (1.0 - 0.5 * h_b) * bnd], axis=0)
+    ni = len(pts)
     x = np.ascontiguousarray(np.concatenate([pts, bnd], axis=0))
-    eligible = np.zeros(n_int + n_bnd, np.uint8)
-    eligible[:n_int] = 1
-    return dict(x=x, n_int=n_int, n_bnd=n_bnd, eligible=eligible,
-                boundary=np.arange(n_int, n_int + n_bnd, dtype=np.int32),
+    eligible = np.zeros(ni + n_bnd, np.uint8)
+    eligible[:ni] = 1
+    return dict(x=x, n_int=ni, n_bnd=n_bnd, eligible=eligible,
+                boundary=np.arange(ni, ni + n_bnd, dtype=np.int32),
                 normals=np.ascontiguousarray(bnd))
 
 

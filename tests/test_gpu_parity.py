@@ -62,6 +62,9 @@ CASES = {
     # decides which rows a stencil keeps; tau = 1 is the paper's condition
     "disk5k_d0_tau1": dict(kind="disk", N=5000, n=31, m=5, l=4, delta=0.0,
                            tau=1.0),
+    # boundary refinement (a layer copied h_b/2 inside the boundary)
+    "disk5k_refined_d05": dict(kind="disk_refined", N=5000, n=31, m=5, l=4,
+                               delta=0.5),
     "ball20k_d0_tau2": dict(kind="ball", N=20000, n=50, m=5, l=3, delta=0.0,
                             tau=2.0),
     "ball1237_d0": dict(kind="ball", N=1237, n=20, m=3, l=2, delta=0.0),
@@ -87,8 +90,8 @@ def make(case):
     el = bnd = nrm = None
     if c["kind"] == "square":
         x = nodesets.square(45, 0)
-    elif c["kind"] == "disk":
-        D = nodesets.disk(c["N"], 200, 1)
+    elif c["kind"] in ("disk", "disk_refined"):
+        D = nodesets.disk(c["N"], 200, 1, refine=c["kind"] == "disk_refined")
         x, el, bnd, nrm = D["x"], D["eligible"], D["boundary"], D["normals"]
     else:
         x = nodesets.ball(c["N"], 2)["x"]

@@ -44,3 +44,20 @@ def test_batch_and_request_specs():
     r = nodesets.request_specs(100, 10.0)
     assert all(5e3 - 200 <= q["N"] <= 5e5 + 2000 for q in r)
     assert all(b["t"] > a["t"] for a, b in zip(r, r[1:]))
+
+
+def test_disk_refined():
+    """Boundary refinement: interior within 1 - h_b, then one copy of each
+    boundary node h_b/2 inside along -n (eligible), then the boundary."""
+    import math
+    D = nodesets.disk(3000, 150, 4, refine=True)
+    x, nb = D["x"], 150
+    h_b = 2 * math.pi / nb
+    assert D["n_int"] == 3000 + nb and len(x) == 3000 + 2 * nb
+    r = np.linalg.norm(x, axis=1)
+    assert r[:3000].max() <= 1 - h_b + 1e-12
+    copies, bnd = x[3000:3000 + nb], x[D["boundary"]]
+    assert np.abs(r[D["boundary"]] - 1).max() < 1e-14
+    assert np.abs(copies - (1 - 0.5 * h_b) * bnd).max() < 1e-15
+    assert np.array_equal(D["normals"], bnd)
+    assert D["eligible"][:3000 + nb].all() and not D["eligible"][3000 + nb:].any()

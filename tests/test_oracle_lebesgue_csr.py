@@ -122,3 +122,18 @@ def test_gershgorin_small_matrix():
     assert np.array_equal(d, [-4.0, 0.0, 0.5])
     assert np.array_equal(r, [1.5, 0.0, 5.0])
     assert s == (5.5, -5.5, 1)
+
+
+def test_boundary_refinement_shrinks_neumann_lebesgue():
+    """Sec. 6: adding a layer of nodes just inside the boundary shrinks the
+    Neumann-Lebesgue function at the boundary nodes (Lambda = sum |w| of
+    each normal-derivative row), which is why the paper refines its
+    Neumann node sets."""
+    vals = {}
+    for refine in (False, True):
+        D = nodesets.disk(5000, 200, 1, refine=refine)
+        r = oracle.build_dm(D["x"], 31, 5, 4, 0.5, eligible=D["eligible"],
+                            boundary=D["boundary"], normals=D["normals"])
+        vals[refine] = np.abs(r["W"][D["boundary"]]).sum(1)
+    assert vals[True].mean() < 0.95 * vals[False].mean()
+    assert vals[True].max() < vals[False].max()
