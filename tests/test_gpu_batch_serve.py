@@ -214,6 +214,44 @@ def test_server_alone_equals_mix(orbf):
     srv.close()
 
 
+def test_moving_nodes_rebuilt_each_step(orbf):
+    """Dynamic domains (Sec. 8 motivates per-step rebuilds for moving
+    nodes): a 20k-node ball that moves each step (rotation about z plus a
+    small random drift) is rebuilt through the request engine every step.
+    Every step's DM equals a direct build of the same nodes bit for bit, and
+    the first step's stencils and covering equal the oracle's."""
+    ctx = orbf.Context(0)
+    x0 = nodesets.ball(20000, 2)["x"]
+    rng = np.random.default_rng(5)
+    n, m, l, delta = 50, 5, 3, 0.3
+    srv = orbf.Server(0, slots=2, arena=2 << 30, slot_scratch=512 << 20)
+    x = x0.copy()
+    lat = []
+    for step in range(6):
+        th = 0.02 * step
+        R = np.array([[np.cos(th), -np.sin(th), 0.0],
+                      [np.sin(th), np.cos(th), 0.0], [0.0, 0.0, 1.0]])
+        x = x0 @ R.T + 1e-4 * rng.standard_normal(x0.shape)
+        xd = gpu(x)
+        t = srv.submit(xd, n, m, l, delta)
+        _drain(srv, [t])
+        info = srv.result(t)
+        assert info["status"] == 0
+        lat.append(1e3 * (info["t_done"] - info["t_arrival"]))
+        got = srv.fetch(t)
+        ref = orbf.build_dm(xd, n, m, l, delta, ctx=ctx)
+        same(got, ref)
+        if step == 0:
+            idx, rho2 = oracle.knn(x, n)
+            owner, _ = oracle.cover(x, idx, rho2, delta)
+            assert np.array_equal(got["knn"].cpu().numpy(), idx)
+            assert np.array_equal(got["owner"].cpu().numpy(), owner)
+        srv.release(t)
+    _say(f"[gpu] moving 20k-node ball: rebuild latency per step (ms) "
+         f"{['%.2f' % v for v in lat]}")
+    srv.close()
+
+
 def test_server_budget_admission(orbf):
     """With an arena that holds about two requests at a time, requests wait
     for memory, the head is passed a bounded number of times, and every
