@@ -22,7 +22,10 @@ namespace {
 
 constexpr int kWaves = 4;    // wavefronts per block in the query kernel
 constexpr int kKeep = 256;   // LDS capacity for ranked candidates per wave
-constexpr int kRun = 16;     // consecutive (cell-ordered) queries per wave
+// consecutive (cell-ordered) queries per wave: 16 in 3D, 8 in 2D (1M-node
+// ball: 2.86 ms at 16, 2.89 at 8, 3.18 at 32; 100k-node disk: 0.293 ms at
+// 16, 0.258 at 8)
+__host__ __device__ constexpr int run_length(int d) { return d == 2 ? 8 : 16; }
 // first threshold: kGrow x the previous query's n-th squared distance; small
 // enough that about n (1 + 1.5 (kGrow - 1)) candidates pass, so most sets fit
 // one key per lane, large enough that few queries need a second pass
@@ -346,8 +349,9 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const GridParams g = *gpp;
   double est = 0.0;  // previous query's n-th squared distance (0: none)
-  const int64_t q_begin = ((int64_t)blockIdx.x * kWaves + w) * kRun;
-  const int64_t q_end = min(q_begin + kRun, N);
+  const int run = run_length(d);
+  const int64_t q_begin = ((int64_t)blockIdx.x * kWaves + w) * run;
+  const int64_t q_end = min(q_begin + run, N);
 
   for (int64_t qs = q_begin; qs < q_end; ++qs) {
     const int32_t qi = perm[qs];
@@ -527,7 +531,8 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   if (st) return st;
   hipLaunchKernelGGL(cell_scatter_kernel, dim3(g1), dim3(256), 0, s, xyz, N, d,
                      cell_of, rank, cstart, perm, xs);
-  const int64_t qblocks = (N + kWaves * kRun - 1) / (kWaves * kRun);
+  const int64_t per_block = (int64_t)kWaves * run_length(d);
+  const int64_t qblocks = (N + per_block - 1) / per_block;
   hipLaunchKernelGGL(knn_query_kernel, dim3((unsigned)qblocks),
                      dim3(64 * kWaves), 0, s, xs, perm, cstart, gp, N, d, n,
                      knn, rho2, d2, ctx->status);
