@@ -21,6 +21,8 @@ namespace orbf {
 
 namespace {
 
+constexpr int64_t kSolveGrid = 4096;  // accept-mode solve blocks per round
+
 enum : int32_t {
   L_UNDECIDED = 0,
   L_PENDING = 1,   // center whose acceptance bits are not computed yet
@@ -53,11 +55,14 @@ __device__ __forceinline__ bool kept(const uint64_t* acc, uint32_t e) {
   return (acc[2 * (int64_t)c + (q >> 6)] >> (q & 63)) & 1ull;
 }
 
-// counters: [0] undecided after the pass, [1] new centers
+// counters: [0] undecided after the pass, [1] new centers; the new centers
+// are also appended to list (count *npend), in no particular order: each
+// is solved on its own
 __global__ __launch_bounds__(256) void ldecide_kernel(
     const uint32_t* __restrict__ pred, const int64_t* __restrict__ start,
     const uint64_t* __restrict__ acc, int64_t N, int32_t* state,
-    int32_t* __restrict__ counters) {
+    int32_t* __restrict__ counters, int32_t* __restrict__ list,
+    int64_t* __restrict__ npend) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= N) return;
   if (state[j] != L_UNDECIDED) return;
@@ -77,16 +82,10 @@ __global__ __launch_bounds__(256) void ldecide_kernel(
   } else if (settled) {
     state[j] = L_PENDING;
     atomicAdd(&counters[1], 1);
+    list[atomicAdd((unsigned long long*)npend, 1ull)] = (int32_t)j;
   } else {
     atomicAdd(&counters[0], 1);
   }
-}
-
-__global__ __launch_bounds__(256) void lflag_kernel(
-    const int32_t* __restrict__ state, int64_t N, int32_t want,
-    int32_t* __restrict__ flag) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j < N) flag[j] = state[j] == want;
 }
 
 __global__ __launch_bounds__(256) void lcompact_kernel(
@@ -100,8 +99,16 @@ __global__ __launch_bounds__(256) void lcompact_kernel(
 __global__ __launch_bounds__(256) void lsolved_kernel(
     const int32_t* __restrict__ list, const int64_t* __restrict__ count,
     int32_t* __restrict__ state) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t < *count) state[list[t]] = L_SOLVED;
+  const int64_t cnt = *count;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < cnt;
+       t += (int64_t)gridDim.x * 256)
+    state[list[t]] = L_SOLVED;
+}
+
+// start of a round: counters and the pending count
+__global__ void lround_zero_kernel(int32_t* counters, int64_t* npend) {
+  if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *npend = 0;
 }
 
 __global__ __launch_bounds__(256) void lowner_kernel(
@@ -181,32 +188,35 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
   P.owner = nullptr;
   P.W = nullptr;
   P.lebesgue = nullptr;
+  // A round decides every node whose predecessors are settled, then solves
+  // the new centers in accept mode and marks them solved.  The kernels read
+  // the pending count on the device, so rounds run back to back and the
+  // host reads the last round's counters only after each batch of rounds;
+  // rounds after the last decision find nothing to do.
+  const unsigned gs = (unsigned)(N < kSolveGrid ? N : kSolveGrid);
+  const unsigned gm = (unsigned)((N + 255) / 256 < 1024 ? (N + 255) / 256 : 1024);
   int32_t hc[2];
-  for (int round = 0;; ++round) {
-    hipLaunchKernelGGL(lzero_kernel, dim3(1), dim3(256), 0, s, counters, 2);
-    hipLaunchKernelGGL(ldecide_kernel, dim3(g), dim3(256), 0, s, pred, pstart,
-                       acc, N, state, counters);
+  int64_t rounds = 0;
+  for (int batch = 1;; batch = batch < 64 ? 2 * batch : 64) {
+    for (int r = 0; r < batch; ++r, ++rounds) {
+      hipLaunchKernelGGL(lround_zero_kernel, dim3(1), dim3(64), 0, s,
+                         counters, npend);
+      hipLaunchKernelGGL(ldecide_kernel, dim3(g), dim3(256), 0, s, pred,
+                         pstart, acc, N, state, counters, list, npend);
+      if (!launch_weights_reg(ctx, P, gs))
+        return fail(ctx, ORBF_EINVAL,
+                    "Lebesgue covering needs the register weights kernel "
+                    "(n + M <= 72, M <= 35)");
+      hipLaunchKernelGGL(lsolved_kernel, dim3(gm), dim3(256), 0, s, list,
+                         npend, state);
+    }
     hipError_t e = hipMemcpyAsync(hc, counters, sizeof hc,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if ((st = hip_check(ctx, e, "Lebesgue covering round"))) return st;
-    if (hc[1] > 0) {
-      hipLaunchKernelGGL(lflag_kernel, dim3(g), dim3(256), 0, s, state, N,
-                         (int32_t)L_PENDING, flag);
-      if ((st = exclusive_scan_i32_to_i64(ctx, flag, N, pos))) return st;
-      hipLaunchKernelGGL(lcompact_kernel, dim3(g1), dim3(256), 0, s, flag, pos,
-                         N, list, npend);
-      const int64_t grid = hc[1];  // one block per pending center
-      if (!launch_weights_reg(ctx, P, grid))
-        return fail(ctx, ORBF_EINVAL,
-                    "Lebesgue covering needs the register weights kernel "
-                    "(n + M <= 72, M <= 35)");
-      hipLaunchKernelGGL(lsolved_kernel, dim3((unsigned)((hc[1] + 255) / 256)),
-                         dim3(256), 0, s, list, npend, state);
-    } else if (hc[0] == 0) {
-      break;
-    }
-    if (round > N + 2)
+    // the last round left no node undecided and made no new center
+    if (hc[0] == 0 && hc[1] == 0) break;
+    if (rounds > N + 2)
       return fail(ctx, ORBF_EINTERNAL, "Lebesgue covering did not settle");
   }
   hipLaunchKernelGGL(lowner_kernel, dim3(g), dim3(256), 0, s, pred, pstart,
