@@ -259,7 +259,8 @@ orbf_status orbf_gershgorin(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
  *   row_kind[e] == 0 : x_e                        (Dirichlet)
  *   any other value  : (L x)_e                    (a boundary-operator row
  *                      of the DM, e.g. a normal derivative for Neumann data)
- * by unpreconditioned BiCGSTAB (van der Vorst 1992), started from x.
+ * by BiCGSTAB (van der Vorst 1992), started from x, unpreconditioned or
+ * with Jacobi right preconditioning (D = diag A).
  *   row_ptr, col, val : the CSR of L (device; as from orbf_assemble_csr)
  *   row_kind : N bytes (device), or NULL for all rows interior
  *   b        : N FP64 right-hand side (device);  x : N FP64 (device), in:
@@ -267,21 +268,28 @@ orbf_status orbf_gershgorin(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
  *              solution
  *   tol      : stop when ||b - A x||_2 <= tol ||b||_2 (the recurrence
  *              residual; ||b|| = 0 is taken as 1)
- *   max_iter : iteration limit;  iters, relres : host outputs (each may be
- *              NULL): iterations done and the final relative residual
+ *   max_iter : iteration limit
+ *   precond  : ORBF_PRECOND_NONE or ORBF_PRECOND_JACOBI.  Jacobi evens out
+ *              the row scales of boundary-operator rows (about 1/h) and
+ *              interior rows (about 1 + dt |L_ee|): it cuts the iterations of
+ *              Neumann steps 2-3x but costs iterations on Dirichlet steps
+ *   iters, relres : host outputs (each may be NULL): iterations done and
+ *              the final relative residual
  * Synchronous: returns after the solve, reading four inner products back
  * to the host per iteration; every inner product is summed in a fixed
  * order, so a solve is deterministic.  Not converging within max_iter, or a
  * BiCGSTAB breakdown, is not an error: relres says how far it got.  Scratch:
- * 7 N FP64 plus 16 KB of the context.
+ * 10 N FP64 plus 16 KB of the context.
  * Errors: EINVAL (N out of range, NULL input, b == x, tol < 0 or NaN,
- * max_iter < 0, alpha or beta not finite), ENOMEM, EHIP. */
+ * max_iter < 0, alpha or beta not finite, unknown precond), ENOMEM,
+ * EHIP. */
+enum { ORBF_PRECOND_NONE = 0, ORBF_PRECOND_JACOBI = 1 };
 orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
                                 const int64_t* row_ptr, const int32_t* col,
                                 const double* val, const uint8_t* row_kind,
                                 double alpha, double beta, const double* b,
                                 double* x, double tol, int max_iter,
-                                int* iters, double* relres);
+                                int precond, int* iters, double* relres);
 
 /* Coefficients of the backward differentiation formula of order k = 1..4
  * (Sec. 5 time-steps with BDF4 and starts it with BDF1-3):

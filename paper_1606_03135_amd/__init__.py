@@ -114,7 +114,7 @@ def lib():
         L.orbf_gershgorin.argtypes = [_P, _I64, _P, _P, _P, _P, _P, _P]
         L.orbf_gershgorin.restype = _I
         L.orbf_solve_implicit.argtypes = [
-            _P, _I64, _P, _P, _P, _P, _D, _D, _P, _P, _D, _I,
+            _P, _I64, _P, _P, _P, _P, _D, _D, _P, _P, _D, _I, _I,
             ctypes.POINTER(_I), ctypes.POINTER(_D)]
         L.orbf_solve_implicit.restype = _I
         L.orbf_bdf_coefficients.argtypes = [_I, ctypes.POINTER(_D),
@@ -346,13 +346,20 @@ def gershgorin(ctx, row_ptr, col, val, rows=True):
     return diag, radius, summary
 
 
+PRECONDS = {"none": 0, "jacobi": 1}
+
+
 def solve_implicit(ctx, row_ptr, col, val, b, *, alpha=1.0, beta=-1.0,
-                   row_kind=None, x0=None, tol=1e-10, max_iter=1000):
+                   row_kind=None, x0=None, tol=1e-10, max_iter=1000,
+                   precond="none"):
     """One implicit time step with a DM (Sec. 5): solve A x = b with row e
     of A equal to alpha x_e + beta (L x)_e where row_kind[e] == 1 (or
     everywhere if ``row_kind`` is None), x_e where it is 0 (Dirichlet) and
-    (L x)_e elsewhere, by BiCGSTAB from ``x0`` (zeros if None).  Returns
-    (x, iterations, relative residual)."""
+    (L x)_e elsewhere, by BiCGSTAB from ``x0`` (zeros if None),
+    ``precond`` "none" or "jacobi".  Returns (x, iterations, relative
+    residual)."""
+    if precond not in PRECONDS:
+        raise ValueError("precond must be 'none' or 'jacobi'")
     row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
     col = _dev(col, torch.int32, "col")
     val = _dev(val, torch.float64, "val")
@@ -373,7 +380,8 @@ def solve_implicit(ctx, row_ptr, col, val, b, *, alpha=1.0, beta=-1.0,
     ctx.check(lib().orbf_solve_implicit(
         ctx._h, N, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(row_kind),
         float(alpha), float(beta), _ptr(b), _ptr(x), float(tol),
-        int(max_iter), ctypes.byref(it), ctypes.byref(res)))
+        int(max_iter), PRECONDS[precond], ctypes.byref(it),
+        ctypes.byref(res)))
     return x, it.value, res.value
 
 
@@ -388,7 +396,8 @@ def bdf_coefficients(order):
 
 
 def bdf_step(ctx, row_ptr, col, val, levels, dt, *, nu=1.0, f=None,
-             row_kind=None, bvals=None, tol=1e-12, max_iter=1000):
+             row_kind=None, bvals=None, tol=1e-12, max_iter=1000,
+             precond="none"):
     """One BDF step of u_t = nu L u + f with the DM (Sec. 5), of order
     len(levels) (1..4; ``levels`` = [u^n, u^{n-1}, ...], newest first):
     orbf_bdf_rhs, then orbf_solve_implicit from u^n.  Returns (u^{n+1},
@@ -415,7 +424,7 @@ def bdf_step(ctx, row_ptr, col, val, levels, dt, *, nu=1.0, f=None,
     _, b = bdf_coefficients(k)
     return solve_implicit(ctx, row_ptr, col, val, rhs, alpha=1.0,
                           beta=-b * nu * dt, row_kind=row_kind, x0=levels[0],
-                          tol=tol, max_iter=max_iter)
+                          tol=tol, max_iter=max_iter, precond=precond)
 
 
 def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,

@@ -361,7 +361,7 @@ orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
                                 const double* val, const uint8_t* row_kind,
                                 double alpha, double beta, const double* b,
                                 double* x, double tol, int max_iter,
-                                int* iters, double* relres) {
+                                int precond, int* iters, double* relres) {
   if (!ctx) return ORBF_EINVAL;
   if (N < 1 || N > INT32_MAX) return fail(ctx, ORBF_EINVAL, "N out of range");
   if (!row_ptr || !col || !val || !b || !x)
@@ -371,9 +371,12 @@ orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
     return fail(ctx, ORBF_EINVAL, "tol >= 0 and max_iter >= 0 required");
   if (!isfinite(alpha) || !isfinite(beta))
     return fail(ctx, ORBF_EINVAL, "alpha and beta must be finite");
+  if (precond != ORBF_PRECOND_NONE && precond != ORBF_PRECOND_JACOBI)
+    return fail(ctx, ORBF_EINVAL, "unknown preconditioner");
   hipSetDevice(ctx->device);
   return launch_solve_implicit(ctx, N, row_ptr, col, val, row_kind, alpha,
-                               beta, b, x, tol, max_iter, iters, relres);
+                               beta, b, x, tol, max_iter, precond, iters,
+                               relres);
 }
 
 orbf_status orbf_bdf_coefficients(int order, double* a, double* b) {

@@ -206,7 +206,7 @@ orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
                                   const double* val, const uint8_t* row_kind,
                                   double alpha, double beta, const double* b,
                                   double* x, double tol, int max_iter,
-                                  int* iters, double* relres);
+                                  int precond, int* iters, double* relres);
 orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        const int32_t* owner, const double* W,
                        int64_t* row_ptr, int32_t* col, double* val);

@@ -63,18 +63,21 @@ def ball_dm():
     return x, oracle.build_dm(x, 50, 5, 3, 0.3)
 
 
-def _check(orbf, ctx, ref, b, kind, alpha, beta, x0=None, tag=""):
+def _check(orbf, ctx, ref, b, kind, alpha, beta, x0=None, tag="",
+           precond="none"):
     rp, col, val = ref["row_ptr"], ref["col"], ref["val"]
     want = oracle.solve_implicit(rp, col, val, b, kind, alpha, beta)
     x, it, res = orbf.solve_implicit(
         ctx, gpu(rp), gpu(col), gpu(val), gpu(b), alpha=alpha, beta=beta,
         row_kind=None if kind is None else gpu(kind),
-        x0=None if x0 is None else gpu(x0), tol=1e-12, max_iter=2000)
+        x0=None if x0 is None else gpu(x0), tol=1e-12, max_iter=2000,
+        precond=precond)
     got = x.cpu().numpy()
     A = oracle.implicit_system(rp, col, val, kind, alpha, beta)
     true_res = np.linalg.norm(b - A @ got) / np.linalg.norm(b)
     err = np.abs(got - want).max() / np.abs(want).max()
-    _say(f"[gpu] solve {tag}: {it} iterations, relres {res:.2e}, "
+    _say(f"[gpu] solve {tag} ({precond}): {it} iterations, "
+         f"relres {res:.2e}, "
          f"true {true_res:.2e}, err vs direct {err:.2e}")
     assert res <= 1e-12
     assert true_res <= 1e-10
@@ -82,9 +85,10 @@ def _check(orbf, ctx, ref, b, kind, alpha, beta, x0=None, tag=""):
     return got, it, res
 
 
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
 @pytest.mark.parametrize("bc,dt", [("dirichlet", 1e-3), ("dirichlet", 1e-2),
                                    ("neumann", 1e-3), ("neumann", 1e-4)])
-def test_heat_step_on_disk(orbf, ctx, disk_dm, bc, dt):
+def test_heat_step_on_disk(orbf, ctx, disk_dm, bc, dt, precond):
     """Backward Euler for u_t = Laplacian u on the disk: the paper's system
     with Dirichlet (boundary rows x_b = 0) or Neumann (the DM's
     normal-derivative rows = 0) data, from u0 = exp(-4 |x|^2)."""
@@ -96,7 +100,8 @@ def test_heat_step_on_disk(orbf, ctx, disk_dm, bc, dt):
     u0 = np.exp(-4.0 * (x ** 2).sum(1))
     b = u0.copy()
     b[kind != 1] = 0.0
-    _check(orbf, ctx, ref, b, kind, 1.0, -dt, x0=u0, tag=f"disk {bc} {dt}")
+    _check(orbf, ctx, ref, b, kind, 1.0, -dt, x0=u0, tag=f"disk {bc} {dt}",
+           precond=precond)
 
 
 def test_all_rows_shifted_ball(orbf, ctx, ball_dm):
@@ -147,9 +152,9 @@ def test_solve_errors(orbf, ctx, disk_dm):
     res = ctypes.c_double(0.0)
     common = (P(rp), P(col), P(val), None)
 
-    def call(n, alpha, beta, bp, xp, tol, mi):
+    def call(n, alpha, beta, bp, xp, tol, mi, pc=0):
         return L.orbf_solve_implicit(ctx._h, n, *common, alpha, beta, bp, xp,
-                                     tol, mi, ctypes.byref(it),
+                                     tol, mi, pc, ctypes.byref(it),
                                      ctypes.byref(res))
 
     x = torch.zeros_like(b)
@@ -160,5 +165,6 @@ def test_solve_errors(orbf, ctx, disk_dm):
     assert call(N, float("inf"), -1e-3, P(b), P(x), 1e-10, 5) == orbf.EINVAL
     assert call(0, 1.0, -1e-3, P(b), P(x), 1e-10, 5) == orbf.EINVAL
     assert call(N, 1.0, -1e-3, None, P(x), 1e-10, 5) == orbf.EINVAL
+    assert call(N, 1.0, -1e-3, P(b), P(x), 1e-10, 5, 2) == orbf.EINVAL
     with pytest.raises(ValueError):
         orbf.solve_implicit(ctx, rp, col, val, b[:-1])
