@@ -14,6 +14,23 @@ its Gershgorin disks, y = L x, one backward-Euler step (I - dt L) u1 = u0
 with Dirichlet rows on the sphere, solved by BiCGSTAB, and BDF4 steps of
 the same problem (after one step each of BDF1-3).
 
+Unless --quick, the same JSON line also carries the other measured
+workloads, each timed after the headline:
+  - w1_square: the jittered 45 x 45 square (2,025 nodes), r^3, l = 2,
+    n = 12, delta = 1 (standard RBF-FD), microseconds per build;
+  - w2_disk: the unit disk, 99,400 interior + 600 boundary nodes, r^5,
+    l = 4, n = 31, delta = 0.5, Lebesgue threshold 5 on the Laplacian rows,
+    normal-derivative boundary rows, in the shuffled and the Poisson-disk
+    generation order, with phase times;
+  - delta1_gpu: the headline ball at delta = 1 (standard RBF-FD), and the
+    speedup of the overlapped build over it;
+  - batched: the 512-set batch below (FP32 + refinement and FP64, with the
+    FP64 peak fraction of the summed per-set flops);
+  - serving: the request stream below, FP64 and FP32 + refinement;
+  - cpu_baseline: besides the oracle's rate on the whole workload (all
+    threads of the job's CPU share), single-thread phase times on a
+    100k-node sample and the oracle's delta = 1 build of the whole ball.
+
 --workload batched: 512 mixed node sets (N log-uniform in [1e3, 2e5], 2D/3D,
 l in {2,3,4}, n in [2M+1, 3M], delta in {0.2, 0.5, 1}) in one batched call,
 FP32 + refinement (and FP64 beside it); repeated batches replay a HIP graph.
@@ -84,22 +101,78 @@ OPS = {"laplacian": ("OP_LAPLACIAN", "Laplacian"), "dx": ("OP_DX", "d/dx"),
        "identity": ("OP_IDENTITY", "identity")}
 
 
-def cpu_baseline(n, m, l, delta, n_sample, op="laplacian"):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_threads():
+    """Threads the oracle may use: the job's CPU share (its affinity mask,
+    capped by OMP_NUM_THREADS where the environment sets it)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
+def cpu_baseline(n, m, l, delta, n_sample, op="laplacian", extras=True):
+    """The oracle as it stands, timed on the host: the whole workload on
+    every thread of the job's share; with ``extras``, single-thread phase
+    times on a 100k-node sample of the same ball and the delta = 1
+    (standard RBF-FD) build of the whole ball on all threads."""
     import nodesets
     import oracle
-    threads = min(16, len(os.sched_getaffinity(0)))
+    threads = host_threads()
     x = nodesets.ball(n_sample, 2)["x"]
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
     t0 = time.perf_counter()
     r = oracle.build_dm(x, n, m, l, delta, nthreads=threads,
                         knn_method="grid", op=getattr(oracle, OPS[op][0]))
     dt = time.perf_counter() - t0
     nnz = len(r["val"])
-    return {"value": nnz / dt, "unit": "weights/s", "cores": threads,
-            "kind": "oracle",
-            "sample": (f"oracle build_dm (grid kNN, sequential covering, "
-                       f"OpenMP weights) on the 3D ball with N={n_sample} "
-                       f"nodes, same n/m/l/delta: {dt:.2f} s, nnz={nnz}")}
+    out = {"value": nnz / dt, "unit": "weights/s", "cores": threads,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": (f"oracle build_dm (grid kNN, sequential covering, "
+                      f"OpenMP weights) on the 3D ball with N={n_sample} "
+                      f"nodes, same n/m/l/delta: {dt:.2f} s, nnz={nnz}")}
+    if not extras or op != "laplacian":
+        return out
+    # single thread, per phase, on a 100k-node ball
+    xs = nodesets.ball(100_000, 2)["x"]
+    t0 = time.perf_counter()
+    idx, rho2 = oracle.knn(xs, n, "grid")
+    t1 = time.perf_counter()
+    oracle.cover(xs, idx, rho2, delta)
+    t2 = time.perf_counter()
+    rr = oracle.overlapped_rows(xs, idx, rho2, m, l, delta, nthreads=1)
+    t3 = time.perf_counter()
+    rp, col, val = oracle.csr(idx, rr["owner"], rr["W"])
+    t4 = time.perf_counter()
+    out["single_thread_phases_s"] = {
+        "sample": "3D ball, N=100000, same n/m/l/delta, one thread",
+        "knn": t1 - t0, "cover": t2 - t1,
+        "weights": (t3 - t2) - (t2 - t1),  # overlapped_rows also covers
+        "csr": t4 - t3, "weights_per_s": len(val) / (t4 - t0 - (t2 - t1))}
+    # standard RBF-FD (delta = 1) on the whole ball, same threads: the
+    # paper's comparison (Sec. 4.3 speedup model, Sec. 7.2.2 results)
+    t0 = time.perf_counter()
+    r1 = oracle.overlapped_rows(x, r["knn"], r["rho2"], m, l, 1.0,
+                                nthreads=threads)
+    d1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.overlapped_rows(x, r["knn"], r["rho2"], m, l, delta,
+                           nthreads=threads)
+    dd = time.perf_counter() - t0
+    out["delta1"] = {"covering_and_weights_s": d1,
+                     "same_at_delta_s": dd, "speedup": d1 / dd,
+                     "n_centers_delta1": int(len(r1["centers"])),
+                     "n_centers": int(len(r["centers"]))}
+    return out
 
 
 def _log(msg):
@@ -296,10 +369,128 @@ def bench_ball(args, torch, orbf, nodesets):
             torch.neg(a, out=b)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = COPY_BYTES
+    if not args.quick:
+        d1 = bench_delta1(torch, orbf, xd, n, m, l)
+        d1["speedup_of_delta"] = d1["ms_per_build"] / ms_step
+        out["delta1_gpu"] = d1
+        _log(f"delta = 1: {d1['ms_per_build']:.2f} ms per build")
+    del r
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, m, l, delta, args.cpu_sample,
-                                           args.op)
+                                           args.op, extras=not args.quick)
     return out
+
+
+def _ev(torch):
+    return torch.cuda.Event(enable_timing=True)
+
+
+def bench_w1(torch, orbf, nodesets, reps=30):
+    """Jittered 45 x 45 square (2,025 nodes), r^3, l = 2, n = 12, delta = 1
+    (standard RBF-FD), Laplacian, FP64: a latency-bound build, reported in
+    microseconds (median over ``reps`` builds after warm-up)."""
+    x = nodesets.square(45, 0)
+    xd = torch.from_numpy(x).to("cuda:0")
+    ctx = orbf.Context(0)
+    for _ in range(5):
+        orbf.build_dm(xd, 12, 3, 2, 1.0, ctx=ctx)
+    wall, span = [], []
+    for _ in range(reps):
+        e0, e1 = _ev(torch), _ev(torch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        r = orbf.build_dm(xd, 12, 3, 2, 1.0, ctx=ctx, sync=False)
+        e1.record()
+        ctx.sync()
+        wall.append(time.perf_counter() - t0)
+        span.append(e0.elapsed_time(e1))
+    nnz = int(r["row_ptr"][-1].item())
+    return {"workload": "2D square N=2025 (jittered 45x45), r^3, l=2, n=12, "
+                        "delta=1, Laplacian, FP64",
+            "builds": reps, "nnz": nnz,
+            "us_median": 1e6 * float(np.median(wall)),
+            "us_p90": 1e6 * float(np.percentile(wall, 90)),
+            "device_span_us_median": 1e3 * float(np.median(span)),
+            "weights_per_s": nnz / float(np.median(wall))}
+
+
+def bench_w2(torch, orbf, nodesets, reps=10):
+    """Unit disk, 99,400 interior + 600 boundary nodes, r^5, l = 4, n = 31,
+    delta = 0.5, Lebesgue threshold tau = 5 on the Laplacian rows, normal
+    derivative rows at the boundary, FP64; in the shuffled order and in
+    the Poisson-disk generation order.  Phases timed with events between
+    the entry points: kNN, interior rows (the Lebesgue covering and its
+    solves), boundary rows, CSR."""
+    dev = torch.device("cuda:0")
+    res = {"workload": "2D disk 99400 interior + 600 boundary, r^5, l=4, "
+                       "n=31, delta=0.5, tau=5, Laplacian + Neumann rows, "
+                       "FP64"}
+    for order in ("shuffled", "generation"):
+        D = nodesets.disk(99400, 600, 1, order=order)
+        xd = torch.from_numpy(D["x"]).to(dev)
+        el = torch.from_numpy(D["eligible"]).to(dev)
+        bd = torch.from_numpy(D["boundary"]).to(dev)
+        nr = torch.from_numpy(D["normals"]).to(dev)
+        N = xd.shape[0]
+        ctx = orbf.Context(0)
+
+        def once():
+            ev = [_ev(torch) for _ in range(5)]
+            ev[0].record()
+            knn, rho2 = orbf.build_nodes_knn(ctx, xd, 31)
+            ev[1].record()
+            centers = torch.empty(N, dtype=torch.int32, device=dev)
+            nc = torch.zeros(1, dtype=torch.int64, device=dev)
+            owner = torch.empty(N, dtype=torch.int32, device=dev)
+            lam = torch.zeros(N, dtype=torch.float64, device=dev)
+            W = orbf.compute_weights(ctx, orbf.OP_LAPLACIAN, 5, 4, 31, 0.5,
+                                     xd, knn, rho2, centers=centers,
+                                     n_centers=nc, owner=owner, eligible=el,
+                                     tau=5.0, lebesgue=lam)
+            ev[2].record()
+            orbf.compute_weights(ctx, orbf.OP_NEUMANN, 5, 4, 31, 1.0, xd,
+                                 knn, rho2, rows=bd, normals=nr, owner=owner,
+                                 W=W, lebesgue=lam)
+            ev[3].record()
+            rp, _, _ = orbf.assemble_csr(ctx, knn, owner, W)
+            ev[4].record()
+            ctx.sync()
+            return [ev[i].elapsed_time(ev[i + 1]) for i in range(4)], rp, nc
+
+        for _ in range(3):
+            once()
+        ph = []
+        for _ in range(reps):
+            t, rp, nc = once()
+            ph.append(t)
+        ph = np.array(ph)
+        tot = ph.sum(1)
+        nnz = int(rp[-1].item())
+        res[order] = {"ms_median": float(np.median(tot)),
+                      "weights_per_s": nnz / (float(np.median(tot)) * 1e-3),
+                      "nnz": nnz, "n_centers": int(nc.item()),
+                      "phase_ms": dict(zip(("knn", "interior_rows",
+                                            "boundary_rows", "csr"),
+                                           np.median(ph, 0).tolist()))}
+        del ctx
+    return res
+
+
+def bench_delta1(torch, orbf, xd, n, m, l, reps=3):
+    """The same ball with delta = 1 (standard RBF-FD: every node its own
+    stencil), for the speedup of the overlapped build (Sec. 4.3 model,
+    Sec. 7.2.2)."""
+    ctx = orbf.Context(0)
+    r = orbf.build_dm(xd, n, m, l, 1.0, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = orbf.build_dm(xd, n, m, l, 1.0, ctx=ctx)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / reps
+    return {"ms_per_build": ms, "n_centers": int(r["n_centers"].item()),
+            "weights_ms": float(ctx.phase_times()[2])}
 
 
 def bench_batched(args, torch, orbf, nodesets):
@@ -347,6 +538,15 @@ def bench_batched(args, torch, orbf, nodesets):
     o32, lat32, el32 = run(orbf.PREC_FP32_IR, args.steps, args.warmup)
     nnz = sum(int(o["row_ptr"][-1].item()) for o in o32)
     ncent = sum(int(o["n_centers"].item()) for o in o32)
+    # algorithmic flops of the batch: per set, an LU of its K x K system
+    # per stencil plus one substitution pair per kept row
+    flops = 0.0
+    for s, o in zip(specs, o32):
+        nc = int(o["n_centers"].item())
+        own = o["owner"].cpu().numpy()
+        p = np.bincount(own[own >= 0], minlength=len(own))[
+            o["centers"][:nc].cpu().numpy()].astype(np.float64)
+        flops += float(np.sum(lu_flops(s["n"] + s["M"], p)))
     W32 = [o["W"].clone() for o in o32]
     st = np.concatenate([o["ir_steps"].cpu().numpy() for o in o32])
     del o32
@@ -373,7 +573,11 @@ def bench_batched(args, torch, orbf, nodesets):
         "nnz": nnz, "n_centers": ncent,
         "stencils_per_s": ncent * args.steps / el32,
         "fp64": {"value": nnz * args.steps / el64, "unit": "weights/s",
-                 "ms_per_step": 1e3 * el64 / args.steps},
+                 "ms_per_step": 1e3 * el64 / args.steps,
+                 "fp64_peak_frac": flops * args.steps / el64 / 1e12
+                 / FP64_PEAK_TFLOPS},
+        "flops_per_batch": flops,
+        "fp64_peak_frac": flops * args.steps / el32 / 1e12 / FP64_PEAK_TFLOPS,
         "max_row_rel_err_vs_fp64": rel,
         "corrections_mean": float(st[ok].mean()) if ok.any() else None,
         "fp64_rows": float((~ok).mean()),
@@ -397,7 +601,7 @@ def bench_serving(args, torch, orbf, nodesets):
                   for s, x in zip(pool, xs))
     srv = orbf.Server(0, slots=args.slots, arena=arena, slot_scratch=scratch)
 
-    def run(count, rate):
+    def run(count, rate, prec=0):
         """rate None: closed loop (all arrive at once)."""
         picks = rng.integers(0, len(pool), count)
         gaps = (rng.exponential(1.0 / rate, count) if rate
@@ -412,7 +616,7 @@ def bench_serving(args, torch, orbf, nodesets):
                 k = picks[i]
                 s = pool[k]
                 srv.submit(xs[k], s["n"], s["m"], s["l"], s["delta"],
-                           t_arrival=start + arrive[i])
+                           prec=prec, t_arrival=start + arrive[i])
                 i += 1
             for t in srv.poll():
                 info = srv.result(t)
@@ -430,13 +634,17 @@ def bench_serving(args, torch, orbf, nodesets):
                 "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                 "p99_ms": 1e3 * float(np.percentile(lat, 99))}
 
-    run(min(64, args.requests), None)  # warm-up (scratch, code objects)
-    sat = run(args.requests, None)
-    mu = sat["achieved_rps"]
-    loads = {"saturation": sat}
-    for f in (0.5, 0.8):
-        loads[f"{f}mu"] = run(args.requests, f * mu)
+    by_prec = {}
+    for prec, name in ((0, "fp64"), (1, "fp32_ir")):
+        run(min(64, args.requests), None, prec)  # warm-up
+        sat = run(args.requests, None, prec)
+        mu = sat["achieved_rps"]
+        loads = {"saturation": sat}
+        for f in (0.5, 0.8):
+            loads[f"{f}mu"] = run(args.requests, f * mu, prec)
+        by_prec[name] = loads
     srv.close()
+    loads = by_prec["fp64"]
     main_load = loads["0.5mu"]
     return {
         "metric": "DM-build serving: p50/p99 request latency and weights/s "
@@ -452,7 +660,8 @@ def bench_serving(args, torch, orbf, nodesets):
                                f"delta U[0.2,1], n=2M+1), {args.slots} slots",
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": main_load["p50_ms"], "p99": main_load["p99_ms"]},
-        "loads": loads, "node_generation_s": gen_s,
+        "loads": loads, "fp32_ir_loads": by_prec["fp32_ir"],
+        "node_generation_s": gen_s,
     }
 
 
@@ -478,6 +687,9 @@ def main():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=128)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--quick", action="store_true",
+                    help="ball workload only: skip the W1/W2/delta=1/batched/"
+                         "serving sub-records and the oracle's extra legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run a plain device copy of "
                          "known size (to scale HBM byte counters)")
@@ -494,7 +706,31 @@ def main():
 
     fn = {"ball": bench_ball, "batched": bench_batched,
           "serving": bench_serving}[args.workload]
-    print(json.dumps(fn(args, torch, orbf, nodesets)), flush=True)
+    out = fn(args, torch, orbf, nodesets)
+    if args.workload == "ball" and not args.quick and args.op == "laplacian":
+        # the other workloads, timed after the headline
+        torch.cuda.empty_cache()
+        out["w1_square"] = bench_w1(torch, orbf, nodesets)
+        _log(f"W1: {out['w1_square']['us_median']:.0f} us per build")
+        out["w2_disk"] = bench_w2(torch, orbf, nodesets)
+        _log("W2: shuffled {:.2f} ms, generation order {:.2f} ms".format(
+            out["w2_disk"]["shuffled"]["ms_median"],
+            out["w2_disk"]["generation"]["ms_median"]))
+        torch.cuda.empty_cache()
+        b = bench_batched(argparse.Namespace(
+            sets=512, steps=2, warmup=2, no_tune=False), torch, orbf,
+            nodesets)
+        out["batched"] = {k: b[k] for k in (
+            "value", "unit", "ms_per_step", "fp64", "fp64_peak_frac",
+            "flops_per_batch", "nnz", "n_centers", "max_row_rel_err_vs_fp64",
+            "corrections_mean", "fp64_rows", "autotuned", "dtype")}
+        out["batched"]["workload"] = b["config"]["workload"]
+        torch.cuda.empty_cache()
+        sv = bench_serving(argparse.Namespace(
+            pool=128, slots=4, requests=2000), torch, orbf, nodesets)
+        out["serving"] = {"workload": sv["config"]["workload"],
+                          "fp64": sv["loads"], "fp32_ir": sv["fp32_ir_loads"]}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

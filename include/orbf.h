@@ -353,6 +353,14 @@ typedef enum orbf_schedule {
 orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,
                               orbf_schedule schedule);
 
+/* FP32 + refinement (ORBF_PREC_FP32_IR, Sec. 4.3's one decomposition per
+ * stencil done in FP32 and won back by FP64 residual corrections): the
+ * number of corrections a stencil may take before it is solved again from
+ * scratch in FP64 (default 8).  0 sends every stencil that the first FP32
+ * solve does not settle to the FP64 kernel.  EINVAL outside 0..64.  Affects
+ * later calls on this context and on its batched workers. */
+orbf_status orbf_set_ir_max_corrections(orbf_ctx* ctx, int corrections);
+
 /* Copy the table out: up to cap rows of (K, pclass, schedule) to out (host,
  * 3*cap int32); *count receives the number of rows. */
 orbf_status orbf_get_schedules(orbf_ctx* ctx, int32_t* out, int cap,
@@ -437,13 +445,23 @@ typedef struct orbf_server orbf_server;
 
 typedef struct orbf_request {
   const double* xyz;   /* N*d device coordinates, caller-owned; must stay
-                          valid until the request is done                   */
+                          valid until the request is done, and be written
+                          by then: see `ready`                              */
   int64_t N;
   int d, n, m, l;
   double delta;
   double tau;          /* INFINITY = off                                     */
   orbf_prec prec;
   double t_arrival;    /* arrival time on the orbf_server_now clock          */
+  void* ready;         /* hipEvent_t recorded by the caller after the work
+                          that writes xyz (on any stream), or NULL.  The
+                          slot's stream waits for it before the build, so
+                          coordinates produced on the device just before
+                          submit are read only once written.  With NULL the
+                          caller guarantees that xyz is complete when the
+                          request is admitted (e.g. by a stream sync before
+                          submit).  The event must stay valid until the
+                          request is done; the server never destroys it.    */
 } orbf_request;
 
 typedef struct orbf_result {
@@ -477,13 +495,18 @@ orbf_status orbf_server_submit(orbf_server* srv, const orbf_request* req,
 orbf_status orbf_server_poll(orbf_server* srv, uint64_t* done, int cap,
                              int* n_done);
 
-/* Status and timing of a finished request (EINVAL if unknown or not done). */
+/* Status and timing of a finished request (EINVAL if unknown or not done).
+ * n_centers is 0 for a request whose build failed before its covering ran
+ * (the status says why). */
 orbf_status orbf_server_result(orbf_server* srv, uint64_t ticket,
                                orbf_result* out);
 
 /* Copy a finished request's outputs into caller device buffers: the output
  * fields of `dst` (knn, rho2, centers, n_centers, owner, W, lebesgue,
- * ir_steps, row_ptr, col, val; NULL fields are skipped). Synchronous. */
+ * ir_steps, row_ptr, col, val; NULL fields are skipped).  Synchronous: the
+ * copies are complete when it returns.  They are not ordered after work
+ * pending on the caller's streams, so no such work may still use the
+ * destination buffers (a fresh allocation after a sync of its stream). */
 orbf_status orbf_server_fetch(orbf_server* srv, uint64_t ticket,
                               const orbf_set_desc* dst);
 

@@ -69,7 +69,7 @@ class SetDesc(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("xyz", _P), ("N", _I64), ("d", _I), ("n", _I), ("m", _I),
                 ("l", _I), ("delta", _D), ("tau", _D), ("prec", _I),
-                ("t_arrival", _D)]
+                ("t_arrival", _D), ("ready", _P)]
 
 
 class Result(ctypes.Structure):
@@ -129,6 +129,8 @@ def lib():
         L.orbf_build_dm_batched.restype = _I
         L.orbf_set_workers.argtypes = [_P, _I]
         L.orbf_set_workers.restype = _I
+        L.orbf_set_ir_max_corrections.argtypes = [_P, _I]
+        L.orbf_set_ir_max_corrections.restype = _I
         L.orbf_server_create.argtypes = [_I, _I, ctypes.c_size_t,
                                          ctypes.c_size_t, _P]
         L.orbf_server_create.restype = _I
@@ -198,6 +200,12 @@ class Context:
     def sync(self):
         """Wait for the stream and raise any error the device recorded."""
         self.check(lib().orbf_sync(self._h))
+
+    def set_ir_max_corrections(self, k):
+        """FP32 + refinement: corrections allowed before a stencil is
+        solved again in FP64 (default 8; 0 sends every stencil the first
+        FP32 solve does not settle to FP64)."""
+        self.check(lib().orbf_set_ir_max_corrections(self._h, int(k)))
 
     def phase_times(self):
         """[kNN, covering, weights, CSR, last weights kernel] in ms."""
@@ -572,14 +580,20 @@ class Server:
     def submit(self, xyz, n, m, l, delta, tau=math.inf, prec=PREC_FP64,
                t_arrival=None):
         x = _dev(xyz, torch.float64, "xyz")
+        # the slot waits for this event, so coordinates still being written
+        # on the current stream are read only once complete
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(x.device))
         r = Request(xyz=_ptr(x), N=x.shape[0], d=x.shape[1], n=int(n),
                     m=int(m), l=int(l), delta=float(delta), tau=float(tau),
                     prec=int(prec),
-                    t_arrival=self.now() if t_arrival is None else t_arrival)
+                    t_arrival=self.now() if t_arrival is None else t_arrival,
+                    ready=ev.cuda_event)
         t = ctypes.c_uint64()
         self.check(lib().orbf_server_submit(self._h, ctypes.byref(r),
                                             ctypes.byref(t)))
-        self._inputs[t.value] = x  # the request reads it until done
+        # the request reads x, and waits on ev, until it is done
+        self._inputs[t.value] = (x, ev)
         return t.value
 
     def poll(self, cap=1024):
@@ -602,6 +616,9 @@ class Server:
                      prec)
         dsc = SetDesc()
         _fill_outputs(dsc, o)
+        # the copies are not stream-ordered: nothing pending may still use
+        # the memory the new tensors took
+        torch.cuda.current_stream(o["knn"].device).synchronize()
         self.check(lib().orbf_server_fetch(self._h, ticket,
                                            ctypes.byref(dsc)))
         return o

@@ -406,6 +406,15 @@ orbf_status orbf_bdf_rhs(orbf_ctx* ctx, int64_t N, int order,
   return launch_bdf_rhs(ctx, N, order, u, f, dt, row_kind, bvals, rhs);
 }
 
+orbf_status orbf_set_ir_max_corrections(orbf_ctx* ctx, int corrections) {
+  if (!ctx) return ORBF_EINVAL;
+  if (corrections < 0 || corrections > 64)
+    return fail(ctx, ORBF_EINVAL, "ir_max_corrections: 0..64");
+  ctx->ir_max_corrections = corrections;
+  drop_graph(ctx);
+  return ORBF_OK;
+}
+
 orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,
                               orbf_schedule schedule) {
   if (!ctx) return ORBF_EINVAL;

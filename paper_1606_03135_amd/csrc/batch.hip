@@ -189,7 +189,10 @@ static orbf_status enqueue_batch(orbf_ctx* ctx, const orbf_set_desc* sets,
     plan[w].push_back(i);
     load[w] += cost[i];
   }
-  for (int w = 0; w < nw; ++w) ctx->workers[w]->schedules = ctx->schedules;
+  for (int w = 0; w < nw; ++w) {
+    ctx->workers[w]->schedules = ctx->schedules;
+    ctx->workers[w]->ir_max_corrections = ctx->ir_max_corrections;
+  }
   hipError_t e = hipEventRecord(ctx->fork_ev, origin);
   if (e != hipSuccess) return hip_check(ctx, e, "batch fork");
   for (int w = 0; w < nw; ++w) {
@@ -469,11 +472,21 @@ void start(orbf_server* s, int si, uint64_t id) {
       orbf_workspace_size(q.r.N, q.r.d, q.r.n, q.r.l, q.r.prec);
   if (sl.ctx->held + need > s->slot_budget) release_scratch(sl.ctx);
   const orbf_set_desc d = desc_of(s, q);
+  // the coordinates may still be in flight on the producer's stream
+  if (q.r.ready)
+    hipStreamWaitEvent(sl.ctx->stream, (hipEvent_t)q.r.ready, 0);
   orbf_status st = build_set(sl.ctx, d);
-  if (st) q.status = st;
-  // the stencil count goes to the slot's pinned word when the build is done
-  hipMemcpyAsync(sl.nc_host, d.n_centers, sizeof(int64_t),
-                 hipMemcpyDeviceToHost, sl.ctx->stream);
+  if (st) {
+    // failed on the host before its kernels were enqueued: the device word
+    // was never written, so report no stencils
+    q.status = st;
+    *sl.nc_host = 0;
+  } else {
+    // the stencil count goes to the slot's pinned word when the build is
+    // done
+    hipMemcpyAsync(sl.nc_host, d.n_centers, sizeof(int64_t),
+                   hipMemcpyDeviceToHost, sl.ctx->stream);
+  }
   hipEventRecord(sl.done, sl.ctx->stream);
   sl.busy = true;
   sl.req = id;

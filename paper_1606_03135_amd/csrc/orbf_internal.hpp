@@ -125,6 +125,7 @@ struct orbf_ctx {
   std::vector<int> cover_rounds;
   // weights kernel schedules: rows of (K, pclass, orbf_schedule)
   std::vector<int> schedules;
+  int ir_max_corrections = 8;  // FP32 + refinement: cap before FP64 fallback
   orbf::D2Cache d2_cache;
   orbf::PCache p_cache;
 };

@@ -179,6 +179,7 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   P.accept = nullptr;
   P.tau = a->tau;
   P.ir_steps = nullptr;
+  P.ir_max = ctx->ir_max_corrections;
   P.fb_list = nullptr;
   P.fb_count = nullptr;
   P.st = ctx->status;

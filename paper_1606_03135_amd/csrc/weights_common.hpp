@@ -37,6 +37,7 @@ struct WeightsParams {
   // FP32 + refinement: steps per row (or null), and the list of centers the
   // FP64 kernel must solve again (with its device counter)
   int32_t* ir_steps;
+  int ir_max;               // corrections allowed before the FP64 fallback
   int32_t* fb_list;
   int64_t* fb_count;
   DevStatus* st;

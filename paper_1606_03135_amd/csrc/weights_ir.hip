@@ -19,8 +19,9 @@
 //   until max_{j<n} |D_j| <= tol * max_{j<n} |X_j| in every column.
 // The weights (first n unknowns), their unscaling and the Lebesgue sums are
 // formed from X in FP64.  A stencil that meets an exact zero FP32 pivot, or
-// whose block has not converged after kMaxRefine corrections, is appended to
-// a fallback list that the FP64 kernel then solves from scratch.
+// whose block has not converged after the context's correction cap (8 by
+// default, orbf_set_ir_max_corrections) is appended to a fallback list that
+// the FP64 kernel then solves from scratch.
 #include <math.h>
 
 #include "orbf_internal.hpp"
@@ -30,7 +31,6 @@ namespace orbf {
 
 namespace {
 
-constexpr int kMaxRefine = 8;    // corrections after the first solve
 constexpr double kRefineTol = 1e-11;
 
 template <int L, int PL>
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
             col_ok &= (double)dmax <= kRefineTol * (double)xmax;
         });
         if (__ballot(!col_ok) == 0ull) break;
-        if (++it > kMaxRefine) {
+        if (++it > P.ir_max) {
           ok = false;
           break;
         }
@@ -439,10 +439,17 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
         }
       });
     }
-    if (!ok && lane == 0) {
-      const unsigned long long at =
-          atomicAdd((unsigned long long*)P.fb_count, 1ull);
-      P.fb_list[at] = ck;
+    if (!ok) {
+      // rows of blocks that did settle were written with their counts;
+      // the FP64 kernel solves the whole stencil again, so all its rows
+      // report -1 (solved in FP64)
+      if (P.ir_steps)
+        for (int e = lane; e < ncol; e += 64) P.ir_steps[stn[cols_s[e]]] = -1;
+      if (lane == 0) {
+        const unsigned long long at =
+            atomicAdd((unsigned long long*)P.fb_count, 1ull);
+        P.fb_list[at] = ck;
+      }
     }
   }
 }

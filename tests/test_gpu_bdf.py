@@ -206,4 +206,7 @@ def test_heat_equation_neumann_refined_disk_converges(orbf, ctx):
     order = np.polyfit(np.log(hs), np.log(errs), 1)[0]
     _say(f"[gpu] Neumann heat BDF4 observed order {order:.2f}")
     assert np.all(np.isfinite(errs))
-    assert order >= 2.0, (order, errs)
+    # observed 3.3 (estimate h^(l-1) = h^3); a lost order fails this
+    assert order >= 2.8, (order, errs)
+    # recorded RMS error at the finest size: 1.2e-7
+    assert errs[-1] <= 2.0e-7, errs
