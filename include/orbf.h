@@ -223,6 +223,24 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
                               const double* W, int64_t* row_ptr, int32_t* col,
                               double* val);
 
+/* orbf_assemble_csr for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, bit for bit, but the
+ * scratch (row lengths, per-stencil ranks, scan temporaries: about
+ * N * (n + 4) bytes) lives in a fixed 64 MiB device array of the library,
+ * one per device, set up by orbf_create; no call allocates or frees
+ * anything.  Arguments, layout and ownership as for orbf_assemble_csr;
+ * owner must be as the covering makes it (owner[owner[e]] == owner[e]).
+ * Errors: EINVAL as orbf_assemble_csr; EBUDGET if N and n need more than
+ * the 64 MiB (N * n up to about 6.4e7: the 1M-node, n = 50 DM fits).
+ * Calls that overlap on one device share the array and race: serialise
+ * them (one stream, or events). */
+orbf_status orbf_assemble_csr_noalloc(orbf_ctx* ctx, int64_t N, int n,
+                                      const int32_t* knn,
+                                      const int32_t* owner, const double* W,
+                                      int64_t* row_ptr, int32_t* col,
+                                      double* val);
+
 /* y = L x for a DM in CSR: the discrete operator applied to nodal values
  * x (Sec. 4.1: (L f)(x_i) is approximated by sum_j L_ij f(x_j)), the
  * product every use of the DM (time stepping, Krylov solves, Sec. 5) is

@@ -109,6 +109,9 @@ def lib():
         L.orbf_compute_weights.restype = _I
         L.orbf_assemble_csr.argtypes = [_P, _I64, _I, _P, _P, _P, _P, _P, _P]
         L.orbf_assemble_csr.restype = _I
+        L.orbf_assemble_csr_noalloc.argtypes = [_P, _I64, _I, _P, _P, _P, _P,
+                                                _P, _P]
+        L.orbf_assemble_csr_noalloc.restype = _I
         L.orbf_spmv.argtypes = [_P, _I64, _P, _P, _P, _P, _P]
         L.orbf_spmv.restype = _I
         L.orbf_gershgorin.argtypes = [_P, _I64, _P, _P, _P, _P, _P, _P]
@@ -317,6 +320,25 @@ def assemble_csr(ctx, knn, owner, W):
     ctx.check(lib().orbf_assemble_csr(ctx._h, N, n, _ptr(knn), _ptr(owner),
                                       _ptr(W), _ptr(row_ptr), _ptr(col),
                                       _ptr(val)))
+    return row_ptr, col, val
+
+
+def assemble_csr_noalloc(ctx, knn, owner, W, row_ptr, col, val):
+    """``assemble_csr`` into caller-allocated outputs through the
+    allocation-free entry point (its scratch is a fixed device array of the
+    library): row_ptr int64 [N + 1], col int32 [N n], val float64 [N n]."""
+    knn = _dev(knn, torch.int32, "knn")
+    owner = _dev(owner, torch.int32, "owner")
+    W = _dev(W, torch.float64, "W")
+    N, n = knn.shape
+    for t, dt, cnt, name in ((row_ptr, torch.int64, N + 1, "row_ptr"),
+                             (col, torch.int32, N * n, "col"),
+                             (val, torch.float64, N * n, "val")):
+        if _dev(t, dt, name).data_ptr() != t.data_ptr() or t.numel() < cnt:
+            raise ValueError(f"{name}: contiguous {dt}, >= {cnt} entries")
+    ctx.check(lib().orbf_assemble_csr_noalloc(
+        ctx._h, N, n, _ptr(knn), _ptr(owner), _ptr(W), _ptr(row_ptr),
+        _ptr(col), _ptr(val)))
     return row_ptr, col, val
 
 

@@ -154,6 +154,12 @@ orbf_status orbf_create(int device, void* hip_stream, size_t hbm_budget_bytes,
   }
   hipMemset(ctx->status, 0, sizeof(DevStatus));
   for (auto& e : ctx->ev) hipEventCreate(&e);
+  // the allocation-free CSR entry point's scratch on this device
+  if (csr_noalloc_setup(ctx) != ORBF_OK) {
+    const orbf_status st = ORBF_EHIP;
+    orbf_destroy(ctx);
+    return st;
+  }
   *out = ctx;
   return ORBF_OK;
 }
@@ -331,6 +337,21 @@ orbf_status orbf_assemble_csr(orbf_ctx* ctx, int64_t N, int n,
   hipSetDevice(ctx->device);
   PhaseTimer tm(ctx, 3);
   return launch_csr(ctx, N, n, knn, owner, W, row_ptr, col, val);
+}
+
+orbf_status orbf_assemble_csr_noalloc(orbf_ctx* ctx, int64_t N, int n,
+                                      const int32_t* knn,
+                                      const int32_t* owner, const double* W,
+                                      int64_t* row_ptr, int32_t* col,
+                                      double* val) {
+  if (!ctx) return ORBF_EINVAL;
+  if (N < 1 || N > INT32_MAX || n < 1 || n > 128)
+    return fail(ctx, ORBF_EINVAL, "N or n out of range");
+  if (!knn || !owner || !W || !row_ptr || !col || !val)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  hipSetDevice(ctx->device);
+  PhaseTimer tm(ctx, 3);
+  return launch_csr_noalloc(ctx, N, n, knn, owner, W, row_ptr, col, val);
 }
 
 orbf_status orbf_spmv(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,

@@ -3,11 +3,37 @@
 // owner).  Each stencil's n indices (all distinct) are ranked once, by the
 // wavefront of the row that owns itself (its center, or an explicit row);
 // then one thread per entry writes each (index, weight) pair at its rank.
+#include <mutex>
+
 #include "orbf_internal.hpp"
 
 namespace orbf {
 
 namespace {
+
+// Scratch of orbf_assemble_csr_noalloc: row lengths, the stencil ranks and
+// the scan temporaries of one call, laid out at 256-byte offsets.  Every
+// device the library runs on holds one copy until the process ends.  In
+// host code this name is a stand-in, never a device address: the address
+// comes from hipGetSymbolAddress (csr_noalloc_setup).
+constexpr size_t kCsrScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char csr_noalloc_scratch[kCsrScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_csr_mu;
+void* g_csr_scratch[kMaxDevices] = {};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// byte offsets of the three parts for (N, n); total in *bytes
+void csr_noalloc_layout(int64_t N, int n, size_t* off_rank, size_t* off_tmp,
+                        size_t* bytes) {
+  const size_t len = align256((size_t)(N + 1) * 4);
+  const size_t rank = align256((size_t)N * (size_t)n);
+  *off_rank = len;
+  *off_tmp = len + rank;
+  *bytes = len + rank + align256(scan_tmp_elems(N) * sizeof(int64_t));
+}
 
 __global__ __launch_bounds__(256) void row_len_kernel(
     const int32_t* __restrict__ owner, int64_t N, int n,
@@ -71,7 +97,9 @@ __global__ __launch_bounds__(256) void csr_scatter_kernel(
     const int32_t o = owner[e];
     if (o < 0 || o >= N) continue;
     const int64_t so = (int64_t)o * n + q;
-    const int64_t at = row_ptr[e] + crank[so];
+    const int rk = crank[so];
+    if (rk >= n) continue;  // a stale rank (owner o is not a ranked stencil)
+    const int64_t at = row_ptr[e] + rk;
     col[at] = knn[so];
     val[at] = W[e * n + q];
   }
@@ -107,17 +135,20 @@ orbf_status launch_spmv(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
   return hip_check(ctx, hipGetLastError(), "spmv");
 }
 
-orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
-                       const int32_t* owner, const double* W,
-                       int64_t* row_ptr, int32_t* col, double* val) {
+namespace {
+
+// the CSR kernels on given scratch: len (N + 1 int32), crank (N * n bytes),
+// scan temporaries (scan_tmp_elems(N) int64, or null: the context's)
+orbf_status csr_kernels(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
+                        const int32_t* owner, const double* W,
+                        int64_t* row_ptr, int32_t* col, double* val,
+                        int32_t* len, uint8_t* crank, int64_t* scan_tmp) {
   orbf_status st = ORBF_OK;
-  auto* len = (int32_t*)scratch(ctx, B_INDEG, (size_t)(N + 1) * 4, &st);
-  auto* crank = (uint8_t*)scratch(ctx, B_CSR_RANK, (size_t)N * n, &st);
-  if (st) return st;
   hipStream_t s = ctx->stream;
   const unsigned g = (unsigned)((N + 255) / 256);
   hipLaunchKernelGGL(row_len_kernel, dim3(g), dim3(256), 0, s, owner, N, n, len);
-  st = exclusive_scan_i32_to_i64(ctx, len, N, row_ptr);
+  st = scan_tmp ? exclusive_scan_i32_to_i64_tmp(ctx, len, N, row_ptr, scan_tmp)
+                : exclusive_scan_i32_to_i64(ctx, len, N, row_ptr);
   if (st) return st;
   // one wavefront per 64 nodes, four per block
   const dim3 rgrid((unsigned)((N + 255) / 256));
@@ -133,6 +164,56 @@ orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
   hipLaunchKernelGGL(csr_scatter_kernel, grid, dim3(256), 0, s, knn, owner, W,
                      crank, N, n, rpb, row_ptr, col, val);
   return hip_check(ctx, hipGetLastError(), "csr");
+}
+
+}  // namespace
+
+orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
+                       const int32_t* owner, const double* W,
+                       int64_t* row_ptr, int32_t* col, double* val) {
+  orbf_status st = ORBF_OK;
+  auto* len = (int32_t*)scratch(ctx, B_INDEG, (size_t)(N + 1) * 4, &st);
+  auto* crank = (uint8_t*)scratch(ctx, B_CSR_RANK, (size_t)N * n, &st);
+  if (st) return st;
+  return csr_kernels(ctx, N, n, knn, owner, W, row_ptr, col, val, len, crank,
+                     nullptr);
+}
+
+// Once per device, with that device current (orbf_create): the device
+// address of the file-scope array.  Later calls on the same device reuse it.
+orbf_status csr_noalloc_setup(orbf_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return fail(ctx, ORBF_EINVAL, "device index beyond the no-alloc table");
+  std::lock_guard<std::mutex> lock(g_csr_mu);
+  if (!g_csr_scratch[ctx->device]) {
+    void* ptr = nullptr;
+    const hipError_t e =
+        hipGetSymbolAddress(&ptr, HIP_SYMBOL(csr_noalloc_scratch));
+    if (e != hipSuccess || !ptr)
+      return hip_check(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                       "hipGetSymbolAddress(csr no-alloc scratch)");
+    g_csr_scratch[ctx->device] = ptr;
+  }
+  ctx->csr_scratch = g_csr_scratch[ctx->device];
+  return ORBF_OK;
+}
+
+orbf_status launch_csr_noalloc(orbf_ctx* ctx, int64_t N, int n,
+                               const int32_t* knn, const int32_t* owner,
+                               const double* W, int64_t* row_ptr,
+                               int32_t* col, double* val) {
+  size_t off_rank, off_tmp, bytes;
+  csr_noalloc_layout(N, n, &off_rank, &off_tmp, &bytes);
+  if (bytes > kCsrScratchBytes)
+    return fail(ctx, ORBF_EBUDGET,
+                "assemble_csr_noalloc: N * (n + 4) bytes of scratch exceed "
+                "its fixed 64 MiB (N * n <= about 6.4e7)");
+  if (!ctx->csr_scratch)
+    return fail(ctx, ORBF_EHIP, "assemble_csr_noalloc: no scratch address");
+  auto* base = (unsigned char*)ctx->csr_scratch;
+  return csr_kernels(ctx, N, n, knn, owner, W, row_ptr, col, val,
+                     (int32_t*)base, base + off_rank,
+                     (int64_t*)(base + off_tmp));
 }
 
 }  // namespace orbf

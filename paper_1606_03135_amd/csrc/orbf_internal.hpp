@@ -126,6 +126,7 @@ struct orbf_ctx {
   // weights kernel schedules: rows of (K, pclass, orbf_schedule)
   std::vector<int> schedules;
   int ir_max_corrections = 8;  // FP32 + refinement: cap before FP64 fallback
+  void* csr_scratch = nullptr;  // device address of the CSR no-alloc array
   orbf::D2Cache d2_cache;
   orbf::PCache p_cache;
 };
@@ -178,6 +179,10 @@ orbf_status hip_check(orbf_ctx* ctx, hipError_t e, const char* what);
 orbf_status exclusive_scan_i32_to_i64(orbf_ctx* ctx, const int32_t* in,
                                       int64_t n, int64_t* out);
 size_t scan_tmp_elems(int64_t n);  // int64 temporaries of a scan of n
+// the same scan with caller-provided temporaries (scan_tmp_elems(n) int64)
+orbf_status exclusive_scan_i32_to_i64_tmp(orbf_ctx* ctx, const int32_t* in,
+                                          int64_t n, int64_t* out,
+                                          int64_t* tmp);
 
 // phase launchers
 orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
@@ -211,6 +216,13 @@ orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
 orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        const int32_t* owner, const double* W,
                        int64_t* row_ptr, int32_t* col, double* val);
+// allocation-free CSR assembly (csr.hip): device address of the file-scope
+// scratch array on ctx's device, looked up once per device at orbf_create
+orbf_status csr_noalloc_setup(orbf_ctx* ctx);
+orbf_status launch_csr_noalloc(orbf_ctx* ctx, int64_t N, int n,
+                               const int32_t* knn, const int32_t* owner,
+                               const double* W, int64_t* row_ptr,
+                               int32_t* col, double* val);
 
 // retention-ball masks, in-degrees and initial states (cover.hip); uses the
 // kNN's recorded squared distances when they belong to xyz and knn

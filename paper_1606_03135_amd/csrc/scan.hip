@@ -104,6 +104,12 @@ orbf_status exclusive_scan_i32_to_i64(orbf_ctx* ctx, const int32_t* in,
   int64_t* tmp = (int64_t*)scratch(ctx, B_SCAN_TMP,
                                    scan_tmp_elems(n) * sizeof(int64_t), &st);
   if (st) return st;
+  return exclusive_scan_i32_to_i64_tmp(ctx, in, n, out, tmp);
+}
+
+orbf_status exclusive_scan_i32_to_i64_tmp(orbf_ctx* ctx, const int32_t* in,
+                                          int64_t n, int64_t* out,
+                                          int64_t* tmp) {
   if (n == 0) {
     hipLaunchKernelGGL(set_zero_kernel, dim3(1), dim3(1), 0, ctx->stream, out);
     return hip_check(ctx, hipGetLastError(), "scan");
