@@ -61,3 +61,20 @@ def test_disk_refined():
     assert np.abs(copies - (1 - 0.5 * h_b) * bnd).max() < 1e-15
     assert np.array_equal(D["normals"], bnd)
     assert D["eligible"][:3000 + nb].all() and not D["eligible"][3000 + nb:].any()
+
+
+def test_spectrum_dense_block():
+    """Host-side helper of the spectrum diagnostic: the dense block of a
+    small CSR, whole and restricted to a node subset."""
+    from paper_1606_03135_amd import spectrum as spec
+    rp = np.array([0, 2, 3, 5])
+    col = np.array([0, 2, 1, 0, 2])
+    val = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    B = spec.dense_block(rp, col, val)
+    assert np.array_equal(B, [[1, 0, 2], [0, 3, 0], [4, 0, 5]])
+    assert np.array_equal(spec.dense_block(rp, col, val, [0, 2]),
+                          [[1, 2], [4, 5]])
+    # eigenvalues 3 and 3 +- sqrt(12) (the 2 x 2 block [[1, 2], [4, 5]])
+    ev, s = spec.spectrum(rp, col, val)
+    assert s["n_positive_real"] == 2
+    assert abs(s["max_real"] - (3 + 12 ** 0.5)) < 1e-12
