@@ -190,9 +190,19 @@ typedef struct orbf_weights_args {
                             corrections after the first FP32 solve of the
                             row's right-hand-side block; -1 where the row was
                             solved in FP64 (FP32 zero pivot, no convergence
-                            within 8 corrections, n + M > 72, no owner).
-                            Mode (a) rows are always FP64 and leave it
-                            untouched.                                       */
+                            within the correction cap, 8 unless
+                            orbf_set_ir_max_corrections, n + M > 72, no
+                            owner).  Mode (a) rows are always FP64 and leave
+                            it untouched.                                    */
+  int tau_mode;          /* mode (c): how the threshold shrinks a stencil's
+                            retained set.  0: node by node, as `tau` says.
+                            1: radial prefix (the overlap ball shrunk for the
+                            stencil, Sec. 4.2.1 with Sec. 4.4's delta-free
+                            retention): with q* the first stencil position
+                            of an eligible node of the retention ball,
+                            claimed by an earlier center or not, that fails
+                            the test, the center keeps only its unclaimed
+                            eligible ball nodes before q*.  0 when zeroed. */
 } orbf_weights_args;
 
 /* Local weights (Sec. 4.1, eqs. rbffd_linsys, orbffd_eq, orbffd_rhs).
@@ -205,7 +215,11 @@ typedef struct orbf_weights_args {
  * discarded.
  *   op : LAPLACIAN, DX, DY, DZ or IDENTITY in modes (a) and (b); NEUMANN in
  *        mode (a) only; mode (c), the Lebesgue test, with the LAPLACIAN
- *   m  : odd PHS exponent >= 3;  l : polynomial degree >= 0;
+ *   m  : odd PHS exponent >= 3;
+ *   l  : polynomial degree >= 0, or -1 for no polynomial part (M = 0: the
+ *        unaugmented system A w = L phi that Sec. 4.3's cost count also
+ *        covers; A alone can be singular for PHS, reported as ESINGULAR
+ *        only when a pivot is exactly zero);
  *   n  : stencil size (>= M);    delta : overlap parameter in [0,1] (mode c)
  * Errors: EINVAL (parameters, NULL outputs, n + M > 144, mode/op mismatch),
  * ESINGULAR at sync time (exact zero pivot; the stencil's rows are NaN). */
@@ -405,7 +419,7 @@ typedef struct orbf_set_desc {
   int d;                    /* 2 or 3                                        */
   int n;                    /* stencil size                                  */
   int m;                    /* odd PHS exponent >= 3                         */
-  int l;                    /* polynomial degree                             */
+  int l;                    /* polynomial degree (-1: none, M = 0)           */
   double delta;             /* overlap parameter in [0,1]                    */
   double tau;               /* Lebesgue threshold, INFINITY = off            */
   orbf_prec prec;

@@ -60,6 +60,10 @@ def _declare(L):
     L.orc_overlapped_rows.argtypes = [_P, _I64, _I, _I, _I, _I, _P, _P, _D,
                                       _D, _P, _P, _P, _P, _P, _P, _P, _I]
     L.orc_overlapped_rows.restype = _I
+    L.orc_overlapped_rows_mode.argtypes = [_P, _I64, _I, _I, _I, _I, _P, _P,
+                                           _D, _D, _I, _P, _P, _P, _P, _P, _P,
+                                           _P, _I]
+    L.orc_overlapped_rows_mode.restype = _I
     L.orc_overlapped_rows_op.argtypes = [_P, _I64, _I, _I, _I, _I, _I, _P,
                                          _P, _D, _P, _P, _P, _P, _P, _P, _I]
     L.orc_overlapped_rows_op.restype = _I
@@ -163,9 +167,11 @@ def stencil_weights(P, E, m, l, op=OP_LAPLACIAN, normals=None):
 
 
 def overlapped_rows(x, knn_idx, rho2, m, l, delta, tau=np.inf, eligible=None,
-                    nthreads=0):
+                    nthreads=0, prefix=False):
     """Laplacian DM rows with the greedy covering and, for finite tau, the
-    L-Lebesgue acceptance test (Sec. 4.1, Sec. 4.2.1).
+    L-Lebesgue acceptance test (Sec. 4.1, Sec. 4.2.1), node-wise or, with
+    ``prefix``, as the radial prefix of each retention ball (the ball shrunk
+    to just inside its first node that fails the test).
 
     Returns dict(owner, centers, W[N,n] (rows aligned with knn[owner]),
     lam[N], min_margin)."""
@@ -181,12 +187,11 @@ def overlapped_rows(x, knn_idx, rho2, m, l, delta, tau=np.inf, eligible=None,
     W = np.zeros((N, n), np.float64)
     lam = np.zeros(N, np.float64)
     mm = ctypes.c_double()
-    _check(lib().orc_overlapped_rows(_ptr(x), N, d, n, m, l, _ptr(knn_idx),
-                                     _ptr(rho2), float(delta), float(tau),
-                                     _ptr(el), _ptr(owner), _ptr(centers),
-                                     ctypes.byref(nc), _ptr(W), _ptr(lam),
-                                     ctypes.byref(mm), int(nthreads)),
-           "overlapped_rows")
+    _check(lib().orc_overlapped_rows_mode(
+        _ptr(x), N, d, n, m, l, _ptr(knn_idx), _ptr(rho2), float(delta),
+        float(tau), int(bool(prefix)), _ptr(el), _ptr(owner), _ptr(centers),
+        ctypes.byref(nc), _ptr(W), _ptr(lam), ctypes.byref(mm),
+        int(nthreads)), "overlapped_rows")
     return dict(owner=owner, centers=centers[: nc.value].copy(), W=W, lam=lam,
                 min_margin=mm.value)
 
@@ -348,7 +353,8 @@ def bdf_step(row_ptr, col, val, levels, dt, nu=1.0, f=None, row_kind=None,
 
 
 def build_dm(x, n, m, l, delta, tau=np.inf, eligible=None, boundary=None,
-             normals=None, nthreads=0, knn_method="auto", op=OP_LAPLACIAN):
+             normals=None, nthreads=0, knn_method="auto", op=OP_LAPLACIAN,
+             prefix=False):
     """Whole oracle pipeline: stencils, covering (+Lebesgue), interior rows
     of operator ``op`` (the Lebesgue test only with the Laplacian), optional
     normal-derivative rows at ``boundary`` nodes, CSR.  Returns a dict with
@@ -356,7 +362,7 @@ def build_dm(x, n, m, l, delta, tau=np.inf, eligible=None, boundary=None,
     idx, rho2 = knn(x, n, knn_method)
     if op == OP_LAPLACIAN:
         r = overlapped_rows(x, idx, rho2, m, l, delta, tau, eligible,
-                            nthreads)
+                            nthreads, prefix)
     else:
         if not np.isinf(tau):
             raise ValueError("the Lebesgue test is defined for the Laplacian")

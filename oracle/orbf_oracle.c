@@ -411,7 +411,9 @@ static int ge_solve(int K, int R, double* A, double* B) {
 int orc_stencil_weights(int d, int m, int l, int op, int n, const double* P,
                         int ne, const double* E, const double* nrm,
                         double* W) {
-  if ((d != 2 && d != 3) || m < 3 || (m % 2) == 0 || l < 0 || ne < 1)
+  /* l = -1: no polynomial augmentation (M = 0), the unaugmented RBF-FD
+   * system A w = L phi that Sec. 4.3 also counts */
+  if ((d != 2 && d != 3) || m < 3 || (m % 2) == 0 || l < -1 || ne < 1)
     return ORC_EINVAL;
   if (op < ORC_OP_LAPLACIAN || op > ORC_OP_IDENTITY) return ORC_EINVAL;
   if (op == ORC_OP_NEUMANN && nrm == NULL) return ORC_EINVAL;
@@ -616,9 +618,22 @@ int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
                         double tau, const uint8_t* eligible, int32_t* owner,
                         int32_t* centers, int64_t* n_centers, double* Wrows,
                         double* lam, double* min_margin, int nthreads) {
+  return orc_overlapped_rows_mode(x, N, d, n, m, l, knn, rho2, delta, tau, 0,
+                                  eligible, owner, centers, n_centers, Wrows,
+                                  lam, min_margin, nthreads);
+}
+
+int orc_overlapped_rows_mode(const double* x, int64_t N, int d, int n, int m,
+                             int l, const int32_t* knn, const double* rho2,
+                             double delta, double tau, int prefix,
+                             const uint8_t* eligible, int32_t* owner,
+                             int32_t* centers, int64_t* n_centers,
+                             double* Wrows, double* lam, double* min_margin,
+                             int nthreads) {
   if ((d != 2 && d != 3) || n < 1 || n > N || !(delta >= 0.0 && delta <= 1.0))
     return ORC_EINVAL;
   if (!(tau >= 1.0)) return ORC_EINVAL; /* tau = +inf disables the test */
+  if (prefix != 0 && prefix != 1) return ORC_EINVAL;
   if (n < orc_num_monomials(d, l) || m < 3 || m % 2 == 0) return ORC_EINVAL;
   int err = ORC_OK;
   double margin = INFINITY;
@@ -650,7 +665,9 @@ int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
     int ref = centroid_ref(x, d, n, st);
     for (int q = 0; q < n; q++) {
       int32_t j = st[q];
-      if (!elig(eligible, j) || owner[j] != -1) continue;
+      /* the radial prefix tests every eligible node of the ball, claimed
+       * or not: its cut depends on the stencil alone */
+      if (!elig(eligible, j) || (!prefix && owner[j] != -1)) continue;
       if (sqdist(x + k * d, x + (int64_t)j * d, d) <= thr) {
         if (q == ref) ref_col = ne;
         qs[ne++] = q;
@@ -665,19 +682,23 @@ int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
                        P, E, W);
     if (err) break;
     double lref = l1norm(W + ref_col * n, n);
+    /* radial prefix (the ball shrunk for this stencil): nothing at or
+     * beyond the first ball node that fails the test is kept */
+    int cut = ne;
     for (int e = 0; e < ne; e++) {
       int32_t j = st[qs[e]];
       double le = l1norm(W + e * n, n);
       int accept = (qs[e] == 0);
-      if (!accept) {
+      if (!accept && e < cut) {
         accept = le <= tau * lref;
         /* the reference node compares its own column with itself */
         if (qs[e] != ref) {
           double mg = fabs(le - tau * lref) / (tau * lref);
           if (mg < margin) margin = mg;
         }
+        if (!accept && prefix) cut = e;
       }
-      if (!accept) continue;
+      if (!accept || owner[j] != -1) continue;
       owner[j] = (int32_t)k;
       memcpy(Wrows + (int64_t)j * n, W + e * n, sizeof(double) * n);
       if (lam) lam[j] = le;

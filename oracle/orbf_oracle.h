@@ -87,7 +87,8 @@ int orc_cover(const double* x, int64_t N, int d, int n, const int32_t* knn,
  *   nrm : ne*d unit normals (ORC_OP_NEUMANN) or NULL;
  *   W   : ne*n output, W[e*n + j] = weight of stencil node j for point e,
  *         in physical units (the scaled solve is divided by rho^theta).
- * m odd >= 3, l >= 0, n >= C(l+d,d). */
+ * m odd >= 3, l >= -1 (l = -1: no polynomial part, M = 0, the unaugmented
+ * system of Sec. 4.3), n >= C(l+d,d). */
 int orc_stencil_weights(int d, int m, int l, int op, int n, const double* P,
                         int ne, const double* E, const double* nrm,
                         double* W);
@@ -106,6 +107,20 @@ int orc_overlapped_rows(const double* x, int64_t N, int d, int n, int m, int l,
                         double tau, const uint8_t* eligible, int32_t* owner,
                         int32_t* centers, int64_t* n_centers, double* Wrows,
                         double* lam, double* min_margin, int nthreads);
+
+/* orc_overlapped_rows with a choice of how the threshold shrinks a
+ * stencil's retained set: prefix = 0 is node-wise (as above); prefix = 1 is
+ * the radial prefix: with q* the first stencil position of an eligible node
+ * of the retention ball (claimed by an earlier center or not) that fails
+ * Lambda <= tau * Lambda_ref, the center keeps only its unclaimed eligible
+ * ball nodes before q* (its ball shrunk to just inside the first failure). */
+int orc_overlapped_rows_mode(const double* x, int64_t N, int d, int n, int m,
+                             int l, const int32_t* knn, const double* rho2,
+                             double delta, double tau, int prefix,
+                             const uint8_t* eligible, int32_t* owner,
+                             int32_t* centers, int64_t* n_centers,
+                             double* Wrows, double* lam, double* min_margin,
+                             int nthreads);
 
 /* The same rows (infinite tau only) for another operator: LAPLACIAN, DX,
  * DY, DZ (d = 3) or IDENTITY. */

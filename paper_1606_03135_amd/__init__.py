@@ -53,7 +53,8 @@ class WeightsArgs(ctypes.Structure):
                 ("rho2", _P), ("rows", _P), ("n_rows", _I64),
                 ("centers", _P), ("n_centers", _P), ("owner", _P),
                 ("eligible", _P), ("normals", _P), ("tau", _D), ("prec", _I),
-                ("W", _P), ("lebesgue", _P), ("ir_steps", _P)]
+                ("W", _P), ("lebesgue", _P), ("ir_steps", _P),
+                ("tau_mode", _I)]
 
 
 class SetDesc(ctypes.Structure):
@@ -268,7 +269,7 @@ def select_overlapped_stencils(ctx, xyz, knn, rho2, delta, eligible=None):
 def compute_weights(ctx, op, m, l, n, delta, xyz, knn, rho2, *, centers=None,
                     n_centers=None, owner=None, rows=None, normals=None,
                     eligible=None, tau=math.inf, prec=PREC_FP64, W=None,
-                    lebesgue=None, ir_steps=None):
+                    lebesgue=None, ir_steps=None, tau_mode=0):
     """Local weights (Sec. 4.1 eqs. rbffd_linsys / orbffd_eq / orbffd_rhs).
 
     Rows come from the covering (centers, n_centers, owner) or from an
@@ -297,6 +298,7 @@ def compute_weights(ctx, op, m, l, n, delta, xyz, knn, rho2, *, centers=None,
     if eligible is not None:
         a.eligible = _ptr(_dev(eligible, torch.uint8, "eligible"))
     a.tau = float(tau)
+    a.tau_mode = int(tau_mode)
     a.prec = int(prec)
     a.W = _ptr(W)
     a.lebesgue = _ptr(lebesgue)
@@ -459,7 +461,7 @@ def bdf_step(ctx, row_ptr, col, val, levels, dt, *, nu=1.0, f=None,
 
 def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
              boundary=None, normals=None, prec=PREC_FP64, ctx=None,
-             sync=True, op=OP_LAPLACIAN):
+             sync=True, op=OP_LAPLACIAN, tau_mode=0):
     """Whole DM build on the device: stencils, covering, interior rows of
     operator ``op`` (LAPLACIAN, DX, DY, DZ or IDENTITY; a finite ``tau``
     only with the Laplacian), optional normal-derivative rows at
@@ -487,7 +489,7 @@ def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,
     W = compute_weights(ctx, op, m, l, n, delta, xyz, knn, rho2,
                         centers=centers, n_centers=n_centers, owner=owner,
                         eligible=eligible, tau=tau, prec=prec, lebesgue=lam,
-                        ir_steps=ir_steps)
+                        ir_steps=ir_steps, tau_mode=tau_mode)
     if boundary is not None and len(boundary):
         compute_weights(ctx, OP_NEUMANN, m, l, n, 1.0, xyz, knn, rho2,
                         rows=boundary, normals=normals, owner=owner, W=W,

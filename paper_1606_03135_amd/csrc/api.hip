@@ -293,13 +293,17 @@ orbf_status orbf_compute_weights(orbf_ctx* ctx, orbf_op op, int m, int l,
     return fail(ctx, ORBF_EINVAL, "d/dz needs d = 3");
   if (m < 3 || m % 2 == 0)
     return fail(ctx, ORBF_EINVAL, "PHS exponent m must be odd and >= 3");
-  if (l < 0) return fail(ctx, ORBF_EINVAL, "polynomial degree l < 0");
+  // l = -1: no polynomial augmentation (M = 0, K = n), the unaugmented
+  // RBF-FD of Sec. 4.3's count
+  if (l < -1) return fail(ctx, ORBF_EINVAL, "polynomial degree l < -1");
   const int M = num_monomials(a->d, l);
   if (n < M) return fail(ctx, ORBF_EINVAL, "stencil size n < C(l+d, d)");
   if (n + M > 144) return fail(ctx, ORBF_EINVAL, "n + M > 144");
   if (!(delta >= 0.0 && delta <= 1.0))
     return fail(ctx, ORBF_EINVAL, "delta must lie in [0, 1]");
   if (!(a->tau >= 1.0)) return fail(ctx, ORBF_EINVAL, "tau must be >= 1");
+  if (a->tau_mode != 0 && a->tau_mode != 1)
+    return fail(ctx, ORBF_EINVAL, "tau_mode must be 0 or 1");
   if (!a->xyz || !a->knn || !a->rho2 || !a->W)
     return fail(ctx, ORBF_EINVAL, "NULL pointer");
   if (a->prec != ORBF_PREC_FP64 && a->prec != ORBF_PREC_FP32_IR)

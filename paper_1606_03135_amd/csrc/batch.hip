@@ -101,7 +101,7 @@ static bool set_ok(const orbf_set_desc& s, std::string* why) {
     return false;
   }
   const int M = monomials(s.d, s.l);
-  if (s.l < 0 || s.n < M || s.n + M > 160) {
+  if (s.l < -1 || s.n < M || s.n + M > 160) {
     *why = "need C(l+d,d) <= n and n + C(l+d,d) <= 160";
     return false;
   }

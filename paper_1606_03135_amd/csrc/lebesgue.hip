@@ -181,6 +181,8 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
                      ball, pstart, fill, pred);
 
   WeightsParams P = P0;
+  P.eligible = eligible;
+  P.t2 = t2;
   P.ball = ball;
   P.accept = acc;
   P.centers = list;

@@ -178,6 +178,9 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   P.ball = nullptr;
   P.accept = nullptr;
   P.tau = a->tau;
+  P.tau_mode = a->tau_mode;
+  P.eligible = a->eligible;
+  P.t2 = t2;
   P.ir_steps = nullptr;
   P.ir_max = ctx->ir_max_corrections;
   P.fb_list = nullptr;

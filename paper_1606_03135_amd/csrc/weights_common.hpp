@@ -34,6 +34,12 @@ struct WeightsParams {
   const uint64_t* ball;     // 2 words per node: ball positions q (j > c)
   uint64_t* accept;         // 2 words per node: accepted positions q
   double tau;
+  // 0: each ball node kept or rejected on its own; 1: radial prefix (the
+  // ball shrunk to just inside its first node that fails, claimed or not,
+  // which needs the whole eligible ball: eligibility and (1-delta)^2)
+  int tau_mode;
+  const uint8_t* eligible;
+  double t2;
   // FP32 + refinement: steps per row (or null), and the list of centers the
   // FP64 kernel must solve again (with its device counter)
   int32_t* ir_steps;

@@ -132,17 +132,32 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         }
       }
       const uint64_t b0 = P.ball[2 * (int64_t)ck], b1 = P.ball[2 * (int64_t)ck + 1];
+      // columns: the unclaimed-candidate ball (eligible nodes after the
+      // center, from the covering's masks), or for the radial prefix the
+      // whole eligible ball, tested here exactly as the covering tests it
+      const bool prefix = P.tau_mode == 1;
+      const double thr = prefix ? P.t2 * P.rho2[ck] : 0.0;
+      auto in_cols = [&](int q) -> bool {
+        if (q == 0) return true;
+        if (!prefix) {
+          const uint64_t word = (q < 64) ? b0 : b1;
+          return (word >> (q & 63)) & 1ull;
+        }
+        const int32_t j = stn[q];
+        if (P.eligible != nullptr && P.eligible[j] == 0) return false;
+        const double* xq = P.xyz + (int64_t)j * d;
+        return exact_sqdist(xc[0], xc[1], d == 3 ? xc[2] : 0.0, xq[0], xq[1],
+                            d == 3 ? xq[2] : 0.0, d) <= thr;
+      };
       for (int q0 = 0; q0 < n; q0 += 64) {
         const int q = q0 + lane;
-        const uint64_t word = (q < 64) ? b0 : b1;
-        const bool mine = q < n && (q == 0 || ((word >> (q & 63)) & 1ull));
+        const bool mine = q < n && in_cols(q);
         const unsigned long long b = __ballot(mine);
         if (mine) cols_s[ncol + __popcll(b & ((1ull << lane) - 1ull))] = q;
         if (mine && q == bq) refcol_s = ncol + __popcll(b & ((1ull << lane) - 1ull));
         ncol += __popcll(b);
       }
-      const uint64_t rw = (bq < 64) ? b0 : b1;
-      const bool ref_in = bq == 0 || ((rw >> (bq & 63)) & 1ull);
+      const bool ref_in = in_cols(bq);
       nball = ncol;
       if (!ref_in) {
         if (lane == 0) {
@@ -384,11 +399,28 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
       // keep node e iff it is the center or Lambda_e <= tau * Lambda_ref
       // (eq. calLstab with the threshold tau)
       const double lref = lam_s[refcol_s];
+      // radial prefix: nothing at or after the first failing ball node
+      int efail = nball;
+      if (P.tau_mode == 1) {
+        for (int e0 = 0; e0 < nball; e0 += 64) {
+          const int e = e0 + lane;
+          const bool fails =
+              e < nball && cols_s[e] != 0 && !(lam_s[e] <= P.tau * lref);
+          const unsigned long long fb = __ballot(fails);
+          if (fb) {
+            efail = e0 + __ffsll((long long)fb) - 1;
+            break;
+          }
+        }
+      }
       for (int e = lane; e < nball; e += 64) {  // the appended reference
                                                 // column is not a row
         const int q = cols_s[e];
-        const bool acc = q == 0 || lam_s[e] <= P.tau * lref;
-        if (acc && q != 0) atomicOr(&accw_s[q >> 6], 1ull << (q & 63));
+        const bool acc = q == 0 || (e < efail && lam_s[e] <= P.tau * lref);
+        // only candidate positions (the covering's masks) carry a bit
+        const uint64_t word = P.ball[2 * (int64_t)ck + (q >> 6)];
+        if (acc && q != 0 && ((word >> (q & 63)) & 1ull))
+          atomicOr(&accw_s[q >> 6], 1ull << (q & 63));
       }
       wsync();
       if (lane == 0) {

@@ -82,6 +82,19 @@ CASES = {
     "ball5k_l3_n60_d02": dict(kind="ball", N=5000, n=60, m=5, l=3,
                               delta=0.2),
     "disk5k_l4_n60": dict(kind="disk", N=5000, n=60, m=5, l=4, delta=0.5),
+    # radial prefix: each stencil keeps its retention ball only up to the
+    # first node that fails the Lebesgue test (the ball shrunk per stencil)
+    "disk5k_d0_tau1_prefix": dict(kind="disk", N=5000, n=31, m=5, l=4,
+                                  delta=0.0, tau=1.0, prefix=True),
+    "disk5k_d03_tau1_prefix": dict(kind="disk", N=5000, n=31, m=5, l=4,
+                                   delta=0.3, tau=1.0, prefix=True),
+    "ball20k_d0_tau2_prefix": dict(kind="ball", N=20000, n=50, m=5, l=3,
+                                   delta=0.0, tau=2.0, prefix=True),
+    # no polynomial part (l = -1, M = 0): unaugmented RBF-FD (Sec. 4.3)
+    "disk5k_unaug_d05": dict(kind="disk", N=5000, n=31, m=5, l=-1,
+                             delta=0.5),
+    "ball20k_unaug_d03": dict(kind="ball", N=20000, n=50, m=3, l=-1,
+                              delta=0.3),
 }
 
 
@@ -106,8 +119,10 @@ def test_build_dm_matches_oracle(orbf, ctx, case):
     x, el, bnd, nrm, c = make(case)
     _say(f"[gpu] build_dm {case} N={len(x)} n={c['n']} delta={c['delta']}")
     tau = c.get("tau", math.inf)
+    prefix = c.get("prefix", False)
     ref = oracle.build_dm(x, c["n"], c["m"], c["l"], c["delta"], tau=tau,
-                          eligible=el, boundary=bnd, normals=nrm)
+                          eligible=el, boundary=bnd, normals=nrm,
+                          prefix=prefix)
     if not math.isinf(tau):
         # decisions this close to the threshold may round either way
         _say(f"[gpu] {case}: oracle Lebesgue margin {ref['min_margin']:.2e}")
@@ -115,7 +130,8 @@ def test_build_dm_matches_oracle(orbf, ctx, case):
     got = orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"], tau=tau,
                         eligible=None if el is None else gpu(el),
                         boundary=None if bnd is None else gpu(bnd),
-                        normals=None if nrm is None else gpu(nrm), ctx=ctx)
+                        normals=None if nrm is None else gpu(nrm), ctx=ctx,
+                        tau_mode=int(prefix))
     knn = got["knn"].cpu().numpy()
     assert np.array_equal(knn, ref["knn"])
     assert np.array_equal(got["rho2"].cpu().numpy(), ref["rho2"])
@@ -305,7 +321,7 @@ def test_bitwise_repeatable(orbf, ctx):
 
 
 IR_CASES = ["square45_d05", "square45_d1", "disk5k_d05", "ball20k_d03",
-            "ball1237_d0", "disk5k_d03_tau1"]
+            "ball1237_d0", "disk5k_d03_tau1", "ball20k_unaug_d03"]
 
 
 @pytest.mark.parametrize("case", IR_CASES)

@@ -159,3 +159,71 @@ def test_oracle_matches_rational_case():
     assert r["centers"].tolist() == [c["center"] for c in g["centers"]]
     # decisions are far from the threshold, so FP64 rounding cannot flip one
     assert r["min_margin"] > 1e-3
+
+
+def _replay_prefix(x, idx, rho2, eligible, delta, tau, owner, centers, m, l):
+    """Radial prefix: with q* the first eligible ball node (claimed or not,
+    center excluded) failing the test, c keeps exactly its unclaimed ball
+    nodes before q*.  Returns the number of centers whose ball was cut."""
+    t = 1.0 - delta
+    t2 = t * t
+    cuts = 0
+    for c in centers:
+        st = idx[c]
+        thr = t2 * rho2[c]
+        ball = [q for q, j in enumerate(st)
+                if (eligible is None or eligible[j])
+                and _sqd(x[c], x[j]) <= thr]
+        assert ball[0] == 0
+        ref = _reference(x[st])
+        W = oracle.stencil_weights(x[st], x[st[[ref] + ball]], m, l)
+        lam = np.abs(W).sum(1)
+        lref = lam[0]
+        qstar = len(st)
+        for i, q in enumerate(ball[1:], start=2):
+            if not lam[i] <= tau * lref:
+                qstar = q
+                break
+        cuts += qstar < len(st)
+        want = {st[q] for q in ball if q < qstar and owner[st[q]] >= c}
+        got = set(np.nonzero(owner == c)[0].tolist())
+        assert got == want, (c, sorted(got ^ want))
+    return cuts
+
+
+@pytest.mark.parametrize("delta,tau", [(0.0, 1.0), (0.0, 2.0), (0.3, 1.0)])
+def test_radial_prefix_disk(disk4k, delta, tau):
+    D, idx, rho2 = disk4k
+    el = D["eligible"]
+    r = oracle.overlapped_rows(D["x"], idx, rho2, 5, 4, delta, tau, el,
+                               prefix=True)
+    assert (r["owner"][el == 1] >= 0).all()
+    cuts = _replay_prefix(D["x"], idx, rho2, el, delta, tau, r["owner"],
+                          r["centers"], 5, 4)
+    assert cuts > 0
+    # the same threshold node by node keeps at least as much per stencil,
+    # so it never needs more stencils
+    nw = oracle.overlapped_rows(D["x"], idx, rho2, 5, 4, delta, tau, el)
+    assert len(r["centers"]) >= len(nw["centers"])
+
+
+@pytest.mark.parametrize("delta,tau", [(0.0, 1.0), (0.3, 2.0)])
+def test_radial_prefix_ball(ball3k, delta, tau):
+    x, idx, rho2 = ball3k
+    r = oracle.overlapped_rows(x, idx, rho2, 5, 3, delta, tau, None,
+                               prefix=True)
+    cuts = _replay_prefix(x, idx, rho2, None, delta, tau, r["owner"],
+                          r["centers"], 5, 3)
+    assert cuts > 0
+
+
+def test_radial_prefix_without_threshold_is_plain_covering(disk4k):
+    """tau = infinity cuts nothing: the prefix mode is then the plain greedy
+    covering (Sec. 4.1)."""
+    D, idx, rho2 = disk4k
+    el = D["eligible"]
+    a = oracle.overlapped_rows(D["x"], idx, rho2, 5, 4, 0.3, np.inf, el,
+                               prefix=True)
+    own, cen = oracle.cover(D["x"], idx, rho2, 0.3, el)
+    assert np.array_equal(a["owner"], own)
+    assert np.array_equal(a["centers"], cen)

@@ -121,10 +121,12 @@ def test_row_sums_vanish():
 
 
 @pytest.mark.parametrize("d,m,l,n,op", [(2, 3, 2, 12, 0), (2, 5, 2, 14, 1),
-                                        (3, 3, 1, 12, 0), (2, 5, 3, 16, 0)])
+                                        (3, 3, 1, 12, 0), (2, 5, 3, 16, 0),
+                                        (2, 3, -1, 12, 0), (3, 5, -1, 16, 1)])
 def test_mpmath_bruteforce(d, m, l, n, op):
     """40-digit solve of the same saddle system, assembled from sympy
-    derivatives of |x - y|^m, against the FP64 oracle."""
+    derivatives of |x - y|^m, against the FP64 oracle (l = -1: no
+    polynomial block, the unaugmented system A w = L phi)."""
     mpmath.mp.dps = 40
     rng = np.random.default_rng(11 + n + op)
     P = _stencil(rng, d, n)
