@@ -315,13 +315,57 @@ orbf_status orbf_gershgorin(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
  * Errors: EINVAL (N out of range, NULL input, b == x, tol < 0 or NaN,
  * max_iter < 0, alpha or beta not finite, unknown precond), ENOMEM,
  * EHIP. */
-enum { ORBF_PRECOND_NONE = 0, ORBF_PRECOND_JACOBI = 1 };
+enum {
+  ORBF_PRECOND_NONE = 0,
+  ORBF_PRECOND_JACOBI = 1,
+  ORBF_PRECOND_ILU0 = 2  /* orbf_solve_implicit_krylov only */
+};
 orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
                                 const int64_t* row_ptr, const int32_t* col,
                                 const double* val, const uint8_t* row_kind,
                                 double alpha, double beta, const double* b,
                                 double* x, double tol, int max_iter,
                                 int precond, int* iters, double* relres);
+
+/* ILU(0) of the implicit step matrix A of orbf_solve_implicit (rows chosen
+ * by row_kind, alpha, beta), the preconditioner Secs. 7.1 and 7.2 use:
+ * Gaussian elimination restricted to A's sparsity pattern, which is the
+ * DM's (for each row i and each k < i in it, ascending: a_ik /= a_kk, then
+ * a_ij -= a_ik a_kj for the j > k present in both rows).  L (unit lower)
+ * and U are written to lu, aligned with the CSR (lu[t] belongs to col[t]).
+ * Every row must hold its diagonal (DM rows do).
+ *   row_ptr, col, val : the CSR of L (device);  row_kind, alpha, beta : as
+ *   for orbf_solve_implicit;  lu : nnz FP64 output (device, not aliasing
+ *   val)
+ * Asynchronous.  One launch factors all rows: each row waits for the rows
+ * it depends on, in order.  Errors: EINVAL (sizes, NULL, lu == val); at
+ * sync time EINVAL (a row without a diagonal entry), ESINGULAR (a zero
+ * pivot), EINTERNAL (a bounded wait ran out).  Scratch: 16 N bytes. */
+orbf_status orbf_implicit_ilu0(orbf_ctx* ctx, int64_t N,
+                               const int64_t* row_ptr, const int32_t* col,
+                               const double* val, const uint8_t* row_kind,
+                               double alpha, double beta, double* lu);
+
+/* The implicit step of orbf_solve_implicit with a choice of Krylov method
+ * and preconditioner (Sec. 5; Sec. 7.1 uses GMRES with ILU(0) in 2D, Sec.
+ * 7.2 BiCGSTAB with ILU(0) in 3D):
+ *   method   : ORBF_KRYLOV_BICGSTAB, or ORBF_KRYLOV_GMRES (restarted after
+ *              `restart` steps, 1..64; classical Gram-Schmidt twice)
+ *   precond  : ORBF_PRECOND_NONE, _JACOBI, or _ILU0 with lu from
+ *              orbf_implicit_ilu0 of the same row_kind, alpha and beta (right
+ *              preconditioning: A M^-1 y = b, x = M^-1 y)
+ * Other arguments, stopping rule and outputs as for orbf_solve_implicit
+ * (GMRES stops on its residual estimate and reports the true residual of
+ * the last restart).  Synchronous.  Scratch: BiCGSTAB 10 N FP64, GMRES
+ * (restart + 5) N FP64, ILU(0) 16 N bytes, plus 0.6 MB.
+ * Errors: as orbf_solve_implicit; EINVAL also for an unknown method, a
+ * restart out of range, ILU0 without lu. */
+enum { ORBF_KRYLOV_BICGSTAB = 0, ORBF_KRYLOV_GMRES = 1 };
+orbf_status orbf_solve_implicit_krylov(
+    orbf_ctx* ctx, int64_t N, const int64_t* row_ptr, const int32_t* col,
+    const double* val, const uint8_t* row_kind, double alpha, double beta,
+    const double* b, double* x, double tol, int max_iter, int method,
+    int restart, int precond, const double* lu, int* iters, double* relres);
 
 /* Coefficients of the backward differentiation formula of order k = 1..4
  * (Sec. 5 time-steps with BDF4 and starts it with BDF1-3):

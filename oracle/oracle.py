@@ -298,6 +298,102 @@ def implicit_system(row_ptr, col, val, row_kind, alpha, beta):
     return A.tocsr()
 
 
+def step_values(row_ptr, col, val, row_kind, alpha, beta):
+    """Values of the implicit step matrix (``implicit_system``) on the DM's
+    own sparsity pattern, aligned with ``col`` (zeros kept)."""
+    A = implicit_system(row_ptr, col, val, row_kind, alpha, beta)
+    N = len(row_ptr) - 1
+    rows = np.repeat(np.arange(N), np.diff(row_ptr))
+    return np.asarray(A[rows, col]).ravel()
+
+
+def ilu0(row_ptr, col, a):
+    """ILU(0) of the CSR matrix (row_ptr, col, a), columns ascending in each
+    row: Gaussian elimination with no fill outside the sparsity pattern.
+    For each row i and each k < i in row i, in ascending order,
+    a_ik = a_ik / a_kk, then a_ij = a_ij - a_ik a_kj for every j > k that
+    both rows hold.  Returns the values of L (unit lower, strictly below the
+    diagonal) and U (on and above) aligned with ``col``."""
+    lu = np.array(a, dtype=float)
+    N = len(row_ptr) - 1
+    pos = []   # per row: column -> position
+    diag = np.empty(N, np.int64)
+    for i in range(N):
+        s0, s1 = int(row_ptr[i]), int(row_ptr[i + 1])
+        pos.append({int(c): t for t, c in enumerate(col[s0:s1], start=s0)})
+        if i not in pos[i]:
+            raise ValueError(f"row {i} has no diagonal entry")
+        diag[i] = pos[i][i]
+    for i in range(N):
+        s0, s1 = int(row_ptr[i]), int(row_ptr[i + 1])
+        for t in range(s0, s1):
+            k = int(col[t])
+            if k >= i:
+                break
+            lu[t] = lu[t] / lu[diag[k]]
+            for u in range(int(diag[k]) + 1, int(row_ptr[k + 1])):
+                j = int(col[u])
+                q = pos[i].get(j)
+                if q is not None:
+                    lu[q] = lu[q] - lu[t] * lu[u]
+    return lu
+
+
+def bicgstab(A, b, x0, tol, max_iter, ilu=None):
+    """BiCGSTAB (van der Vorst, 1992; the paper's 3D solver, Sec. 7.2),
+    right-preconditioned with ILU(0) factors ``ilu`` = (row_ptr, col, lu),
+    as ``ilu0`` returns them for that pattern, or unpreconditioned (None).
+    Stops when ||r|| / ||b|| <= tol, checked after each half step (on s)
+    and each full step.  A is any scipy sparse matrix.
+    Returns (x, iterations, relative residual)."""
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spl
+    N = A.shape[0]
+    if ilu is None:
+        def M(v):
+            return v
+    else:
+        F = sps.csr_matrix((ilu[2], ilu[1], ilu[0]), shape=A.shape)
+        L = sps.tril(F, -1, format="csr") + sps.identity(N, format="csr")
+        U = sps.triu(F, 0, format="csr")
+
+        def M(v):
+            y = spl.spsolve_triangular(L, v, lower=True, unit_diagonal=True)
+            return spl.spsolve_triangular(U, y, lower=False)
+    x = np.array(x0, dtype=float)
+    b = np.asarray(b, dtype=float)
+    nb = np.linalg.norm(b) or 1.0
+    r = b - A @ x
+    rh = r.copy()
+    res = np.linalg.norm(r) / nb
+    rho = al = om = 1.0
+    v = np.zeros(N)
+    p = np.zeros(N)
+    it = 0
+    while res > tol and it < max_iter:
+        rho_new = rh @ r
+        if rho_new == 0.0:
+            break
+        it += 1
+        p = r + (rho_new / rho) * (al / om) * (p - om * v)
+        ph = M(p)
+        v = A @ ph
+        al = rho_new / (rh @ v)
+        s = r - al * v
+        if np.linalg.norm(s) / nb <= tol:
+            x = x + al * ph
+            res = np.linalg.norm(s) / nb
+            break
+        sh = M(s)
+        t = A @ sh
+        om = (t @ s) / (t @ t)
+        x = x + al * ph + om * sh
+        r = s - om * t
+        rho = rho_new
+        res = np.linalg.norm(r) / nb
+    return x, it, res
+
+
 def solve_implicit(row_ptr, col, val, b, row_kind=None, alpha=1.0,
                    beta=-1.0):
     """x = A^{-1} b for the matrix of ``implicit_system`` (Sec. 5), by a

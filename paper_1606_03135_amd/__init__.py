@@ -121,6 +121,13 @@ def lib():
             _P, _I64, _P, _P, _P, _P, _D, _D, _P, _P, _D, _I, _I,
             ctypes.POINTER(_I), ctypes.POINTER(_D)]
         L.orbf_solve_implicit.restype = _I
+        L.orbf_implicit_ilu0.argtypes = [_P, _I64, _P, _P, _P, _P, _D, _D,
+                                         _P]
+        L.orbf_implicit_ilu0.restype = _I
+        L.orbf_solve_implicit_krylov.argtypes = [
+            _P, _I64, _P, _P, _P, _P, _D, _D, _P, _P, _D, _I, _I, _I, _I, _P,
+            ctypes.POINTER(_I), ctypes.POINTER(_D)]
+        L.orbf_solve_implicit_krylov.restype = _I
         L.orbf_bdf_coefficients.argtypes = [_I, ctypes.POINTER(_D),
                                              ctypes.POINTER(_D)]
         L.orbf_bdf_coefficients.restype = _I
@@ -378,20 +385,48 @@ def gershgorin(ctx, row_ptr, col, val, rows=True):
     return diag, radius, summary
 
 
-PRECONDS = {"none": 0, "jacobi": 1}
+PRECONDS = {"none": 0, "jacobi": 1, "ilu0": 2}
+
+
+def implicit_ilu0(ctx, row_ptr, col, val, *, alpha=1.0, beta=-1.0,
+                  row_kind=None):
+    """ILU(0) factors of the implicit step matrix (``orbf_implicit_ilu0``,
+    the preconditioner of Secs. 7.1 and 7.2): a device tensor aligned with
+    ``col``, L strictly below the diagonal (unit diagonal implied), U on and
+    above."""
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    val = _dev(val, torch.float64, "val")
+    N = row_ptr.numel() - 1
+    if row_kind is not None:
+        row_kind = _dev(row_kind, torch.uint8, "row_kind")
+        if row_kind.numel() != N:
+            raise ValueError("row_kind must have one entry per DM row")
+    lu = torch.empty_like(val)
+    ctx.check(lib().orbf_implicit_ilu0(ctx._h, N, _ptr(row_ptr), _ptr(col),
+                                       _ptr(val), _ptr(row_kind),
+                                       float(alpha), float(beta), _ptr(lu)))
+    return lu
+
+
+METHODS = {"bicgstab": 0, "gmres": 1}
 
 
 def solve_implicit(ctx, row_ptr, col, val, b, *, alpha=1.0, beta=-1.0,
                    row_kind=None, x0=None, tol=1e-10, max_iter=1000,
-                   precond="none"):
+                   precond="none", method="bicgstab", restart=30, lu=None):
     """One implicit time step with a DM (Sec. 5): solve A x = b with row e
     of A equal to alpha x_e + beta (L x)_e where row_kind[e] == 1 (or
     everywhere if ``row_kind`` is None), x_e where it is 0 (Dirichlet) and
-    (L x)_e elsewhere, by BiCGSTAB from ``x0`` (zeros if None),
-    ``precond`` "none" or "jacobi".  Returns (x, iterations, relative
-    residual)."""
+    (L x)_e elsewhere, from ``x0`` (zeros if None), by ``method``
+    "bicgstab" or "gmres" (restarted after ``restart`` steps), ``precond``
+    "none", "jacobi" or "ilu0" (``lu`` from ``implicit_ilu0`` of the same
+    alpha, beta and row_kind; computed here if None).  Returns (x,
+    iterations, relative residual)."""
     if precond not in PRECONDS:
-        raise ValueError("precond must be 'none' or 'jacobi'")
+        raise ValueError("precond must be 'none', 'jacobi' or 'ilu0'")
+    if method not in METHODS:
+        raise ValueError("method must be 'bicgstab' or 'gmres'")
     row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
     col = _dev(col, torch.int32, "col")
     val = _dev(val, torch.float64, "val")
@@ -409,11 +444,25 @@ def solve_implicit(ctx, row_ptr, col, val, b, *, alpha=1.0, beta=-1.0,
         raise ValueError("x0 must have one entry per DM row")
     it = _I(0)
     res = _D(0.0)
-    ctx.check(lib().orbf_solve_implicit(
+    if method == "bicgstab" and precond != "ilu0":
+        ctx.check(lib().orbf_solve_implicit(
+            ctx._h, N, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(row_kind),
+            float(alpha), float(beta), _ptr(b), _ptr(x), float(tol),
+            int(max_iter), PRECONDS[precond], ctypes.byref(it),
+            ctypes.byref(res)))
+        return x, it.value, res.value
+    if precond == "ilu0" and lu is None:
+        lu = implicit_ilu0(ctx, row_ptr, col, val, alpha=alpha, beta=beta,
+                           row_kind=row_kind)
+    if lu is not None:
+        lu = _dev(lu, torch.float64, "lu")
+        if lu.numel() != val.numel():
+            raise ValueError("lu must be aligned with col")
+    ctx.check(lib().orbf_solve_implicit_krylov(
         ctx._h, N, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(row_kind),
         float(alpha), float(beta), _ptr(b), _ptr(x), float(tol),
-        int(max_iter), PRECONDS[precond], ctypes.byref(it),
-        ctypes.byref(res)))
+        int(max_iter), METHODS[method], int(restart), PRECONDS[precond],
+        _ptr(lu), ctypes.byref(it), ctypes.byref(res)))
     return x, it.value, res.value
 
 
@@ -429,11 +478,13 @@ def bdf_coefficients(order):
 
 def bdf_step(ctx, row_ptr, col, val, levels, dt, *, nu=1.0, f=None,
              row_kind=None, bvals=None, tol=1e-12, max_iter=1000,
-             precond="none"):
+             precond="none", method="bicgstab", restart=30, lu=None):
     """One BDF step of u_t = nu L u + f with the DM (Sec. 5), of order
     len(levels) (1..4; ``levels`` = [u^n, u^{n-1}, ...], newest first):
-    orbf_bdf_rhs, then orbf_solve_implicit from u^n.  Returns (u^{n+1},
-    iterations, relative residual)."""
+    orbf_bdf_rhs, then the implicit solve from u^n (``method``,
+    ``precond``, ``lu`` as for ``solve_implicit``; an ILU(0) ``lu`` must be
+    that of beta = -b_k nu dt).  Returns (u^{n+1}, iterations, relative
+    residual)."""
     k = len(levels)
     if not 1 <= k <= 4:
         raise ValueError("BDF order must be 1..4")
@@ -456,7 +507,8 @@ def bdf_step(ctx, row_ptr, col, val, levels, dt, *, nu=1.0, f=None,
     _, b = bdf_coefficients(k)
     return solve_implicit(ctx, row_ptr, col, val, rhs, alpha=1.0,
                           beta=-b * nu * dt, row_kind=row_kind, x0=levels[0],
-                          tol=tol, max_iter=max_iter, precond=precond)
+                          tol=tol, max_iter=max_iter, precond=precond,
+                          method=method, restart=restart, lu=lu)
 
 
 def build_dm(xyz, n, m, l, delta, *, tau=math.inf, eligible=None,

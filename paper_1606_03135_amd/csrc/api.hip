@@ -147,7 +147,7 @@ orbf_status orbf_create(int device, void* hip_stream, size_t hbm_budget_bytes,
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&ctx->host_counter, sizeof(int64_t),
                     hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&ctx->host_scalars, 4 * sizeof(double),
+      hipHostMalloc((void**)&ctx->host_scalars, 128 * sizeof(double),
                     hipHostMallocDefault) != hipSuccess) {
     delete ctx;
     return ORBF_ENOMEM;
@@ -249,7 +249,7 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   t += want(Nn * 12) + want(24);        // B_CLASS, B_CLASS_N
   t += want(Nn * 4);                    // B_P_CACHE
   t += want(gershgorin_scratch_bytes()); // B_GERSH
-  t += want(krylov_scratch_bytes(N));   // B_KRYLOV
+  t += want(krylov_scratch_bytes(N, 0));  // B_KRYLOV (BiCGSTAB)
   return t;
 }
 
@@ -400,8 +400,52 @@ orbf_status orbf_solve_implicit(orbf_ctx* ctx, int64_t N,
     return fail(ctx, ORBF_EINVAL, "unknown preconditioner");
   hipSetDevice(ctx->device);
   return launch_solve_implicit(ctx, N, row_ptr, col, val, row_kind, alpha,
-                               beta, b, x, tol, max_iter, precond, iters,
-                               relres);
+                               beta, b, x, tol, max_iter, precond, nullptr, 0,
+                               0, iters, relres);
+}
+
+orbf_status orbf_implicit_ilu0(orbf_ctx* ctx, int64_t N,
+                               const int64_t* row_ptr, const int32_t* col,
+                               const double* val, const uint8_t* row_kind,
+                               double alpha, double beta, double* lu) {
+  if (!ctx) return ORBF_EINVAL;
+  if (N < 1 || N > INT32_MAX) return fail(ctx, ORBF_EINVAL, "N out of range");
+  if (!row_ptr || !col || !val || !lu)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  if (lu == val) return fail(ctx, ORBF_EINVAL, "lu and val must not alias");
+  if (!isfinite(alpha) || !isfinite(beta))
+    return fail(ctx, ORBF_EINVAL, "alpha and beta must be finite");
+  hipSetDevice(ctx->device);
+  return launch_ilu0(ctx, N, row_ptr, col, val, row_kind, alpha, beta, lu);
+}
+
+orbf_status orbf_solve_implicit_krylov(
+    orbf_ctx* ctx, int64_t N, const int64_t* row_ptr, const int32_t* col,
+    const double* val, const uint8_t* row_kind, double alpha, double beta,
+    const double* b, double* x, double tol, int max_iter, int method,
+    int restart, int precond, const double* lu, int* iters, double* relres) {
+  if (!ctx) return ORBF_EINVAL;
+  if (N < 1 || N > INT32_MAX) return fail(ctx, ORBF_EINVAL, "N out of range");
+  if (!row_ptr || !col || !val || !b || !x)
+    return fail(ctx, ORBF_EINVAL, "NULL pointer");
+  if (b == x) return fail(ctx, ORBF_EINVAL, "b and x must not alias");
+  if (!(tol >= 0.0) || max_iter < 0)
+    return fail(ctx, ORBF_EINVAL, "tol >= 0 and max_iter >= 0 required");
+  if (!isfinite(alpha) || !isfinite(beta))
+    return fail(ctx, ORBF_EINVAL, "alpha and beta must be finite");
+  if (method != ORBF_KRYLOV_BICGSTAB && method != ORBF_KRYLOV_GMRES)
+    return fail(ctx, ORBF_EINVAL, "unknown Krylov method");
+  if (method == ORBF_KRYLOV_GMRES && (restart < 1 || restart > 64))
+    return fail(ctx, ORBF_EINVAL, "GMRES restart must be in 1..64");
+  if (precond != ORBF_PRECOND_NONE && precond != ORBF_PRECOND_JACOBI &&
+      precond != ORBF_PRECOND_ILU0)
+    return fail(ctx, ORBF_EINVAL, "unknown preconditioner");
+  if (precond == ORBF_PRECOND_ILU0 && !lu)
+    return fail(ctx, ORBF_EINVAL, "ILU(0) preconditioning needs lu");
+  hipSetDevice(ctx->device);
+  return launch_solve_implicit(ctx, N, row_ptr, col, val, row_kind, alpha,
+                               beta, b, x, tol, max_iter, precond, lu, method,
+                               restart, iters, relres);
 }
 
 orbf_status orbf_bdf_coefficients(int order, double* a, double* b) {

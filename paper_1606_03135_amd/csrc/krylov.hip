@@ -7,8 +7,13 @@
 // Sec. 5 (BDF4 takes beta = -(12/25) nu dt): interior rows of I - nu dt L,
 // boundary rows that impose the boundary condition.
 //
-// BiCGSTAB (van der Vorst, 1992), unpreconditioned or with Jacobi right
-// preconditioning (A D^-1 y = b, x = D^-1 y, D = diag A).  A
+// Two Krylov methods, each unpreconditioned or right-preconditioned
+// (A M^-1 y = b, x = M^-1 y) with Jacobi (M = diag A) or with the ILU(0)
+// factors of A (ilu.hip), which is what Secs. 7.1 and 7.2 use:
+//   - BiCGSTAB (van der Vorst, 1992);
+//   - GMRES(m) with classical Gram-Schmidt applied twice, Givens rotations
+//     on the host and restarts after m steps.
+// A
 // normal-derivative row scales like 1/h and an interior row like
 // 1 + dt |L_ee|: on Neumann steps Jacobi cuts the iterations 2-3x, on
 // Dirichlet and all-interior steps it costs iterations (disk at dt = 1e-2:
@@ -17,6 +22,9 @@
 // order (per-block partials, then one wavefront), so a solve is
 // deterministic.  The host drives the iteration and reads each inner
 // product back (pinned memory), four times per iteration.
+#include <algorithm>
+#include <vector>
+
 #include "orbf_internal.hpp"
 
 namespace orbf {
@@ -24,6 +32,7 @@ namespace orbf {
 namespace {
 
 constexpr int kDotBlocks = 1024;
+constexpr int kMaxRestart = 64;  // GMRES(m): m <= 64
 
 __global__ __launch_bounds__(256) void apply_kernel(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
@@ -192,6 +201,96 @@ __global__ __launch_bounds__(256) void bdf_rhs_kernel(
   }
 }
 
+// per-block partials of v_i . w for the k vectors v_i = V + i N
+__global__ __launch_bounds__(256) void mdot_kernel(
+    const double* __restrict__ V, int k, const double* __restrict__ w,
+    int64_t N, double* __restrict__ part) {
+  __shared__ double s[4][kMaxRestart + 1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = 0; i < k; ++i) {
+    const double* v = V + (int64_t)i * N;
+    double u = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < N;
+         t += (int64_t)gridDim.x * 256)
+      u = fma(v[t], w[t], u);
+    for (int o = 32; o >= 1; o >>= 1) u += __shfl_xor(u, o, 64);
+    if (lane == 0) s[wv][i] = u;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += 256)
+    part[(int64_t)blockIdx.x * (kMaxRestart + 1) + i] =
+        ((s[0][i] + s[1][i]) + s[2][i]) + s[3][i];
+}
+
+// out[i] = sum over blocks of part[b][i], i < k, in a fixed order
+__global__ __launch_bounds__(64) void mdot_final_kernel(
+    const double* __restrict__ part, int nparts, int k,
+    double* __restrict__ out) {
+  for (int i = 0; i < k; ++i) {
+    double u = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += 64)
+      u += part[(int64_t)b * (kMaxRestart + 1) + i];
+    for (int o = 32; o >= 1; o >>= 1) u += __shfl_xor(u, o, 64);
+    if (threadIdx.x == 0) out[i] = u;
+  }
+}
+
+// w -= sum_i h[i] v_i with h on the device; acc[i] += h[i] (one thread)
+__global__ __launch_bounds__(256) void msub_kernel(
+    const double* __restrict__ V, int k, const double* __restrict__ h,
+    int64_t N, double* __restrict__ w, double* __restrict__ acc) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < N;
+       t += (int64_t)gridDim.x * 256) {
+    double v = w[t];
+    for (int i = 0; i < k; ++i) v = fma(-h[i], V[(int64_t)i * N + t], v);
+    w[t] = v;
+  }
+  if (acc && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < k; i += 256) acc[i] += h[i];
+}
+
+struct Coeffs {
+  double c[kMaxRestart];
+};
+
+// h[0..k) = 0
+__global__ void lround_zero(double* h, int k) {
+  for (int i = threadIdx.x; i < k; i += 64) h[i] = 0.0;
+}
+
+// out = s * in
+__global__ __launch_bounds__(256) void vscale_kernel(
+    const double* __restrict__ in, double sc, int64_t N,
+    double* __restrict__ out) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < N;
+       t += (int64_t)gridDim.x * 256)
+    out[t] = sc * in[t];
+}
+
+// out = sum_i y_i v_i
+__global__ __launch_bounds__(256) void lincomb_kernel(
+    const double* __restrict__ V, int k, Coeffs y, int64_t N,
+    double* __restrict__ out) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < N;
+       t += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    for (int i = 0; i < k; ++i) v = fma(y.c[i], V[(int64_t)i * N + t], v);
+    out[t] = v;
+  }
+}
+
+// x += z; r = b - y
+__global__ __launch_bounds__(256) void xadd_res_kernel(
+    const double* __restrict__ z, const double* __restrict__ b,
+    const double* __restrict__ y, int64_t N, double* __restrict__ x,
+    double* __restrict__ r) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < N;
+       t += (int64_t)gridDim.x * 256) {
+    if (z) x[t] += z[t];
+    if (r) r[t] = b[t] - y[t];
+  }
+}
+
 }  // namespace
 
 // Backward differentiation formulas (the textbook BDF-k; Sec. 5 uses BDF4
@@ -221,8 +320,11 @@ orbf_status launch_bdf_rhs(orbf_ctx* ctx, int64_t N, int k,
   return hip_check(ctx, hipGetLastError(), "BDF right-hand side");
 }
 
-size_t krylov_scratch_bytes(int64_t N) {
-  return (size_t)N * 10 * 8 + (size_t)kDotBlocks * 2 * 8 + 64;
+size_t krylov_scratch_bytes(int64_t N, int restart) {
+  // BiCGSTAB: ten vectors; GMRES(m): the m + 1 basis vectors and four more
+  const size_t vecs = restart > 0 ? (size_t)restart + 5 : 10;
+  return (size_t)N * vecs * 8 +
+         (size_t)kDotBlocks * (kMaxRestart + 1) * 8 + 64 * 8 * 4;
 }
 
 orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
@@ -230,22 +332,12 @@ orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
                                   const double* val, const uint8_t* row_kind,
                                   double alpha, double beta, const double* b,
                                   double* x, double tol, int max_iter,
-                                  int precond, int* iters, double* relres) {
+                                  int precond, const double* lu, int method,
+                                  int restart, int* iters, double* relres) {
   orbf_status st = ORBF_OK;
-  auto* w = (double*)scratch(ctx, B_KRYLOV, krylov_scratch_bytes(N), &st);
+  const int m = method == 1 ? restart : 0;
+  auto* w = (double*)scratch(ctx, B_KRYLOV, krylov_scratch_bytes(N, m), &st);
   if (st) return st;
-  double* r = w;
-  double* rh = r + N;
-  double* p = rh + N;
-  double* v = p + N;
-  double* s = v + N;
-  double* t = s + N;
-  double* y = t + N;
-  double* dinv = y + N;   // Jacobi (right) preconditioner
-  double* ph = dinv + N;  // dinv * p
-  double* sh = ph + N;    // dinv * s
-  double* part = sh + N;
-  double* out = part + 2 * kDotBlocks;
   hipStream_t sm = ctx->stream;
   const int64_t rows_blocks = (N + 15) / 16;
   const unsigned ga = (unsigned)(rows_blocks < 65536 ? rows_blocks : 65536);
@@ -253,6 +345,8 @@ orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
   const unsigned gv = (unsigned)(vb < 65536 ? vb : 65536);
   const int gd = (int)(vb < kDotBlocks ? vb : kDotBlocks);
   double* h = ctx->host_scalars;
+  double* part = w + (size_t)N * (m > 0 ? (size_t)m + 5 : 10);
+  double* out = part + (size_t)kDotBlocks * (kMaxRestart + 1);
   auto apply = [&](const double* in, double* res) {
     hipLaunchKernelGGL(apply_kernel, dim3(ga), dim3(256), 0, sm, row_ptr, col,
                        val, row_kind, alpha, beta, in, N, res);
@@ -272,8 +366,146 @@ orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
     if (o2) *o2 = h[1];
     return ORBF_OK;
   };
+  // z = M^-1 v (right preconditioner); dinv is the Jacobi diagonal
+  double* dinv = nullptr;
+  auto precondition = [&](const double* v, double* z) -> orbf_status {
+    if (precond == 1) {
+      hipLaunchKernelGGL(scale_kernel, dim3(gv), dim3(256), 0, sm, dinv, v, N,
+                         z);
+      return ORBF_OK;
+    }
+    return launch_ilu_apply(ctx, N, row_ptr, col, lu, v, z);
+  };
+  if (precond == 2 && (st = launch_ilu_prepare(ctx, N, row_ptr, col)))
+    return st;
 
-  if (precond)
+  if (method == 1) {
+    // ---- GMRES(m), right-preconditioned ----
+    double* V = w;                       // m + 1 basis vectors
+    double* z = V + (size_t)(m + 1) * N;  // M^-1 v
+    double* wv = z + N;                  // A z, orthogonalized
+    double* r = wv + N;
+    dinv = r + N;
+    double* hsum = out + kMaxRestart + 1;  // device: h of this column
+    if (precond == 1)
+      hipLaunchKernelGGL(jacobi_kernel, dim3(ga), dim3(256), 0, sm, row_ptr,
+                         col, val, row_kind, alpha, beta, N, dinv);
+    double bb = 0.0, rr = 0.0;
+    apply(x, wv);
+    hipLaunchKernelGGL(xadd_res_kernel, dim3(gv), dim3(256), 0, sm,
+                       (const double*)nullptr, b, wv, N, x, r);
+    if ((st = dots(b, b, r, r, &bb, &rr))) return st;
+    const double nb = bb > 0.0 ? sqrt(bb) : 1.0;
+    double res = sqrt(rr) / nb;
+    int it = 0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+    while (res > tol && it < max_iter) {
+      const double beta0 = sqrt(rr);
+      if (!(beta0 > 0.0)) break;
+      hipLaunchKernelGGL(vscale_kernel, dim3(gv), dim3(256), 0, sm, r,
+                         1.0 / beta0, N, V);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta0;
+      int j = 0;
+      for (; j < m && it < max_iter; ++j) {
+        ++it;
+        const double* vj = V + (size_t)j * N;
+        if (precond) {
+          if ((st = precondition(vj, z))) return st;
+          apply(z, wv);
+        } else {
+          apply(vj, wv);
+        }
+        // classical Gram-Schmidt twice; coefficients stay on the device
+        hipLaunchKernelGGL(lround_zero, dim3(1), dim3(64), 0, sm, hsum,
+                           j + 1);
+        for (int pass = 0; pass < 2; ++pass) {
+          hipLaunchKernelGGL(mdot_kernel, dim3(gd), dim3(256), 0, sm, V,
+                             j + 1, wv, N, part);
+          hipLaunchKernelGGL(mdot_final_kernel, dim3(1), dim3(64), 0, sm,
+                             part, gd, j + 1, out);
+          hipLaunchKernelGGL(msub_kernel, dim3(gv), dim3(256), 0, sm, V,
+                             j + 1, out, N, wv, hsum);
+        }
+        hipLaunchKernelGGL(dot2_kernel, dim3(gd), dim3(256), 0, sm, wv, wv,
+                           (const double*)nullptr, (const double*)nullptr, N,
+                           part);
+        hipLaunchKernelGGL(dot2_final_kernel, dim3(1), dim3(64), 0, sm, part,
+                           gd, hsum + j + 1);
+        hipError_t e = hipMemcpyAsync(h, hsum, (j + 2) * sizeof(double),
+                                      hipMemcpyDeviceToHost, sm);
+        if (e == hipSuccess) e = hipStreamSynchronize(sm);
+        if (e != hipSuccess) return hip_check(ctx, e, "GMRES: Arnoldi");
+        double* col_j = H.data() + (size_t)j * (m + 1);
+        for (int i = 0; i <= j; ++i) col_j[i] = h[i];
+        const double hn = h[j + 1] > 0.0 ? sqrt(h[j + 1]) : 0.0;
+        col_j[j + 1] = hn;
+        // previous rotations, then a new one that zeroes H[j+1][j]
+        for (int i = 0; i < j; ++i) {
+          const double t0 = cs[i] * col_j[i] + sn[i] * col_j[i + 1];
+          col_j[i + 1] = -sn[i] * col_j[i] + cs[i] * col_j[i + 1];
+          col_j[i] = t0;
+        }
+        const double den = hypot(col_j[j], col_j[j + 1]);
+        cs[j] = den > 0.0 ? col_j[j] / den : 1.0;
+        sn[j] = den > 0.0 ? col_j[j + 1] / den : 0.0;
+        col_j[j] = den;
+        col_j[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        res = fabs(g[j + 1]) / nb;
+        if (res <= tol || !(hn > 0.0)) {
+          ++j;
+          break;
+        }
+        if (j + 1 < m)
+          hipLaunchKernelGGL(vscale_kernel, dim3(gv), dim3(256), 0, sm, wv,
+                             1.0 / hn, N, V + (size_t)(j + 1) * N);
+      }
+      // y = R^-1 g (upper triangular, j x j); x += M^-1 V y
+      Coeffs y;
+      for (int i = j - 1; i >= 0; --i) {
+        double v = g[i];
+        for (int k = i + 1; k < j; ++k)
+          v -= H[(size_t)k * (m + 1) + i] * y.c[k];
+        y.c[i] = v / H[(size_t)i * (m + 1) + i];
+      }
+      hipLaunchKernelGGL(lincomb_kernel, dim3(gv), dim3(256), 0, sm, V, j, y,
+                         N, wv);
+      if (precond) {
+        if ((st = precondition(wv, z))) return st;
+        hipLaunchKernelGGL(xadd_res_kernel, dim3(gv), dim3(256), 0, sm, z,
+                           (const double*)nullptr, (const double*)nullptr, N,
+                           x, (double*)nullptr);
+      } else {
+        hipLaunchKernelGGL(xadd_res_kernel, dim3(gv), dim3(256), 0, sm, wv,
+                           (const double*)nullptr, (const double*)nullptr, N,
+                           x, (double*)nullptr);
+      }
+      // the true residual decides
+      apply(x, wv);
+      hipLaunchKernelGGL(xadd_res_kernel, dim3(gv), dim3(256), 0, sm,
+                         (const double*)nullptr, b, wv, N, x, r);
+      if ((st = dots(r, r, nullptr, nullptr, &rr, nullptr))) return st;
+      res = sqrt(rr) / nb;
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = res;
+    return hip_check(ctx, hipGetLastError(), "GMRES");
+  }
+
+  // ---- BiCGSTAB ----
+  double* r = w;
+  double* rh = r + N;
+  double* p = rh + N;
+  double* v = p + N;
+  double* s = v + N;
+  double* t = s + N;
+  double* y = t + N;
+  dinv = y + N;           // Jacobi (right) preconditioner
+  double* ph = dinv + N;  // M^-1 p
+  double* sh = ph + N;    // M^-1 s
+  if (precond == 1)
     hipLaunchKernelGGL(jacobi_kernel, dim3(ga), dim3(256), 0, sm, row_ptr,
                        col, val, row_kind, alpha, beta, N, dinv);
   // without preconditioning the scaled vectors are the vectors themselves
@@ -297,9 +529,7 @@ orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
     const double bt = (rho_new / rho) * (al / om);
     hipLaunchKernelGGL(bicg_p_kernel, dim3(gv), dim3(256), 0, sm, r, v, bt,
                        om, N, p);
-    if (precond)
-      hipLaunchKernelGGL(scale_kernel, dim3(gv), dim3(256), 0, sm, dinv, p, N,
-                         ph);
+    if (precond && (st = precondition(p, ph))) return st;
     apply(ph, v);
     double rhv = 0.0;
     if ((st = dots(rh, v, nullptr, nullptr, &rhv, nullptr))) return st;
@@ -315,9 +545,7 @@ orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
       res = sqrt(ss) / nb;
       break;
     }
-    if (precond)
-      hipLaunchKernelGGL(scale_kernel, dim3(gv), dim3(256), 0, sm, dinv, s, N,
-                         sh);
+    if (precond && (st = precondition(s, sh))) return st;
     apply(sh, t);
     double ts = 0.0, tt = 0.0;
     if ((st = dots(t, s, t, t, &ts, &tt))) return st;

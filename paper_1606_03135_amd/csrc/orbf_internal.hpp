@@ -164,6 +164,7 @@ enum BufId {
   B_P_CACHE,
   B_GERSH,
   B_KRYLOV,
+  B_ILU,
   B_NUM,
 };
 static_assert(B_NUM <= 32, "orbf_ctx::buf holds 32 scratch buffers");
@@ -201,7 +202,18 @@ orbf_status launch_gershgorin(orbf_ctx* ctx, int64_t N,
                               const int64_t* row_ptr, const int32_t* col,
                               const double* val, double* diag, double* radius,
                               double* summary);
-size_t krylov_scratch_bytes(int64_t N);
+size_t krylov_scratch_bytes(int64_t N, int restart);
+// ILU(0) of the implicit step matrix (ilu.hip)
+size_t ilu_scratch_bytes(int64_t N);
+orbf_status launch_ilu0(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
+                        const int32_t* col, const double* val,
+                        const uint8_t* row_kind, double alpha, double beta,
+                        double* lu);
+orbf_status launch_ilu_prepare(orbf_ctx* ctx, int64_t N,
+                               const int64_t* row_ptr, const int32_t* col);
+orbf_status launch_ilu_apply(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
+                             const int32_t* col, const double* lu,
+                             const double* in, double* out);
 void bdf_coefficients(int k, double a[4], double* b);
 orbf_status launch_bdf_rhs(orbf_ctx* ctx, int64_t N, int k,
                            const double* const u[4], const double* f,
@@ -212,7 +224,8 @@ orbf_status launch_solve_implicit(orbf_ctx* ctx, int64_t N,
                                   const double* val, const uint8_t* row_kind,
                                   double alpha, double beta, const double* b,
                                   double* x, double tol, int max_iter,
-                                  int precond, int* iters, double* relres);
+                                  int precond, const double* lu, int method,
+                                  int restart, int* iters, double* relres);
 orbf_status launch_csr(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                        const int32_t* owner, const double* W,
                        int64_t* row_ptr, int32_t* col, double* val);
