@@ -226,7 +226,6 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   // weights in either precision, CSR, Gershgorin disks, implicit solve).
   auto want = [](size_t b) { return (b ? b : 8) + (b ? b : 8) / 8 + 256; };
   const size_t Nn = (size_t)N;
-  const size_t edges = Nn * (size_t)(n > 1 ? n - 1 : 1);
   size_t t = 0;
   t += want(sizeof(GridParams));        // B_GRID_PARAMS
   t += want(1024 * 6 * 8);              // B_PARTIAL
@@ -237,9 +236,9 @@ size_t orbf_workspace_size(int64_t N, int d, int n, int l, orbf_prec prec) {
   t += want(Nn * (size_t)d * 8);        // B_XS
   t += want(Nn * 16);                   // B_BALL
   t += want((Nn + 1) * 4) * 3;          // B_INDEG, B_PRED_FILL, B_ROWPTR_TMP
-  t += want((Nn + 2) * 8) * 2;          // B_PRED_START, B_CENTER_POS
+  t += want((Nn + 2) * 8);              // B_CENTER_POS
   t += want(Nn * 4);                    // B_STATE
-  t += want(edges * 4);                 // B_PRED
+  t += want((Nn + 1) * 12);             // B_PRED (Lebesgue level lists)
   t += want(Nn * 16);                   // B_W_TMP (Lebesgue covering)
   t += want(64) + want(8);              // B_MISC2, B_MISC
   t += want(scan_tmp_elems((int64_t)Nn + 66) * 8);  // B_SCAN_TMP

@@ -7,13 +7,27 @@
 // rule (ascending index) again has a parallel form.  With edges c -> j for
 // eligible j > c in ball(c): j is a center iff every predecessor is a
 // non-center or a center that rejects j; its owner is the smallest
-// predecessor center that keeps it.  Rounds alternate
-//   decide:  undecided nodes whose predecessors are all settled become
-//            covered (some predecessor center keeps them) or centers;
-//   solve:   the new centers solve their ball columns plus the reference
-//            column and record which ball nodes pass the test,
-// until every node is settled.  A final pass computes each row from its
-// owner's stencil.
+// predecessor center that keeps it.
+//
+// The device settles that DAG with work proportional to its edges.  Every
+// node j counts the predecessors that can no longer keep it: non-centers
+// and centers that reject j.  A center that keeps j covers it (and offers
+// itself as j's owner, the smallest offer winning) and never counts off,
+// so a count that reaches zero proves that no predecessor keeps j: j is a
+// center.  A node just covered counts itself off its own ball nodes.
+// Every step is a relaxed atomic on one word; nothing needs ordering
+// across words.
+//
+// A center's keep bits come from solving its stencil (the register kernel
+// in acceptance mode), which needs the center decided first: level k
+// solves the centers decided by level k - 1 and propagates them.  On a
+// scattered numbering the DAG is shallow and a few levels settle it; on a
+// spatially ordered one (a generation front, a raster) it is hundreds of
+// levels deep, and one stencil solve per level would put hundreds of solve
+// latencies on the critical path.  So after a few levels every node still
+// undecided that has a ball is solved at once (its keep bits depend on its
+// own stencil only, whatever it turns out to be), and the rest of the DAG
+// settles by integer propagation alone.
 #include "orbf_internal.hpp"
 #include "weights_common.hpp"
 
@@ -21,71 +35,121 @@ namespace orbf {
 
 namespace {
 
-constexpr int64_t kSolveGrid = 4096;  // accept-mode solve blocks per round
+constexpr int64_t kSolveGrid = 4096;  // accept-mode solve blocks per level
+constexpr unsigned kPropBlocks = 256;   // propagation: 4 wavefronts a block
+constexpr int64_t kSolvedLevels = 4;    // levels solved one by one
 
 enum : int32_t {
   L_UNDECIDED = 0,
-  L_PENDING = 1,   // center whose acceptance bits are not computed yet
-  L_SOLVED = 2,    // center with acceptance bits
-  L_COVERED = 3,   // kept by some earlier center
-  L_INELIGIBLE = 4
+  L_CENTER = 1,   // center (its level solves it)
+  L_COVERED = 2,  // kept by some center
+  L_INELIGIBLE = 3
 };
 
-// predecessor entries carry the stencil position: c | (q << 25)
-__global__ __launch_bounds__(256) void lpred_kernel(
-    const int32_t* __restrict__ knn, int64_t N, int n,
-    const uint64_t* __restrict__ ball, const int64_t* __restrict__ start,
-    int32_t* __restrict__ fill, uint32_t* __restrict__ pred) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= N) return;
-  for (int h = 0; h < 2; ++h) {
-    uint64_t b = ball[2 * c + h];
-    while (b) {
-      const int q = __ffsll((long long)b) - 1 + 64 * h;
-      b &= b - 1;
-      const int32_t j = knn[c * n + q];
-      const int slot = atomicAdd(&fill[j], 1);
-      pred[start[j] + slot] = (uint32_t)c | ((uint32_t)q << 25);
-    }
+__device__ __forceinline__ void push(int32_t* list, int64_t* count,
+                                     int32_t j) {
+  const int64_t slot = __hip_atomic_fetch_add(count, (int64_t)1,
+                                              __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+  list[slot] = j;
+}
+
+// j loses one predecessor that cannot keep it; the last one makes j a
+// center of the next level
+__device__ __forceinline__ void count_off(int32_t* open, int32_t* state,
+                                          int32_t j, int32_t* next,
+                                          int64_t* next_count) {
+  const int32_t left = __hip_atomic_fetch_add(&open[j], -1, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+  if (left == 1) {
+    __hip_atomic_store(&state[j], L_CENTER, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    push(next, next_count, j);
   }
 }
 
-__device__ __forceinline__ bool kept(const uint64_t* acc, uint32_t e) {
-  const uint32_t c = e & 0x1FFFFFFu, q = e >> 25;
-  return (acc[2 * (int64_t)c + (q >> 6)] >> (q & 63)) & 1ull;
-}
-
-// counters: [0] undecided after the pass, [1] new centers; the new centers
-// are also appended to list (count *npend), in no particular order: each
-// is solved on its own
-__global__ __launch_bounds__(256) void ldecide_kernel(
-    const uint32_t* __restrict__ pred, const int64_t* __restrict__ start,
-    const uint64_t* __restrict__ acc, int64_t N, int32_t* state,
-    int32_t* __restrict__ counters, int32_t* __restrict__ list,
-    int64_t* __restrict__ npend) {
+// owners start unset (eligible) or -1; nodes with no predecessor are the
+// first level's centers
+__global__ __launch_bounds__(256) void lseed_kernel(
+    const int32_t* __restrict__ open, int64_t N, int32_t* state,
+    int32_t* __restrict__ owner, int32_t* __restrict__ list,
+    int64_t* __restrict__ count) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= N) return;
-  if (state[j] != L_UNDECIDED) return;
-  bool settled = true, covered = false;
-  for (int64_t t = start[j]; t < start[j + 1]; ++t) {
-    const uint32_t e = pred[t];
-    const int32_t s = __atomic_load_n(&state[e & 0x1FFFFFFu], __ATOMIC_RELAXED);
-    if (s == L_UNDECIDED || s == L_PENDING) {
-      settled = false;
-    } else if (s == L_SOLVED && kept(acc, e)) {
-      covered = true;
-      break;
+  const bool el = state[j] != L_INELIGIBLE;
+  owner[j] = el ? INT32_MAX : -1;
+  if (el && open[j] == 0) {
+    state[j] = L_CENTER;
+    push(list, count, (int32_t)j);
+  }
+}
+
+// every undecided node with a nonempty ball, for the speculative solve
+__global__ __launch_bounds__(256) void lspec_kernel(
+    const int32_t* __restrict__ state, const uint64_t* __restrict__ ball,
+    int64_t N, int32_t* __restrict__ list, int64_t* __restrict__ count) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  if (state[j] == L_UNDECIDED && (ball[2 * j] | ball[2 * j + 1]))
+    push(list, count, (int32_t)j);
+}
+
+// one wavefront per center of the level; lane q takes stencil position q
+// (and q + 64)
+__global__ __launch_bounds__(256) void lprop_kernel(
+    const int32_t* __restrict__ list, const int64_t* __restrict__ count,
+    const int32_t* __restrict__ knn, int n, const uint64_t* __restrict__ ball,
+    const uint64_t* __restrict__ acc, int32_t* open, int32_t* state,
+    int32_t* owner, int32_t* next, int64_t* next_count, int64_t* zero) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *zero = 0;
+  const int lane = threadIdx.x & 63;
+  const int64_t cnt = *count;
+  for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < cnt;
+       w += (int64_t)gridDim.x * 4) {
+    const int32_t c = list[w];
+    for (int h = 0; h < 2 && 64 * h < n; ++h) {
+      const int q = lane + 64 * h;
+      const uint64_t bit = 1ull << lane;
+      if (!(ball[2 * (int64_t)c + h] & bit)) continue;
+      const int32_t j = knn[(int64_t)c * n + q];
+      if (!(acc[2 * (int64_t)c + h] & bit)) {  // c rejects j
+        count_off(open, state, j, next, next_count);
+        continue;
+      }
+      __hip_atomic_fetch_min(&owner[j], c, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      int32_t from = L_UNDECIDED;
+      if (__hip_atomic_compare_exchange_strong(
+              &state[j], &from, L_COVERED, __ATOMIC_RELAXED,
+              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        // j is settled as a non-center: its ball nodes count it off
+        for (int hj = 0; hj < 2 && 64 * hj < n; ++hj) {
+          uint64_t b = ball[2 * (int64_t)j + hj];
+          while (b) {
+            const int qj = __ffsll((long long)b) - 1 + 64 * hj;
+            b &= b - 1;
+            count_off(open, state, knn[(int64_t)j * n + qj], next,
+                      next_count);
+          }
+        }
+      }
     }
   }
-  if (covered) {
-    state[j] = L_COVERED;
-  } else if (settled) {
-    state[j] = L_PENDING;
-    atomicAdd(&counters[1], 1);
-    list[atomicAdd((unsigned long long*)npend, 1ull)] = (int32_t)j;
-  } else {
-    atomicAdd(&counters[0], 1);
+}
+
+// centers own themselves; flags for the ascending center list
+__global__ __launch_bounds__(256) void lfinal_kernel(
+    const int32_t* __restrict__ state, int64_t N, int32_t* __restrict__ owner,
+    int32_t* __restrict__ is_center, DevStatus* st) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  const int32_t s = state[j];
+  if (s == L_CENTER) owner[j] = (int32_t)j;
+  if (s == L_UNDECIDED) {  // the levels ended before the DAG settled
+    report(st, ORBF_EINTERNAL, (int)j);
+    owner[j] = -1;
   }
+  is_center[j] = s == L_CENTER;
 }
 
 __global__ __launch_bounds__(256) void lcompact_kernel(
@@ -96,41 +160,12 @@ __global__ __launch_bounds__(256) void lcompact_kernel(
   if (j < N && flag[j]) list[pos[j]] = (int32_t)j;
 }
 
-__global__ __launch_bounds__(256) void lsolved_kernel(
-    const int32_t* __restrict__ list, const int64_t* __restrict__ count,
-    int32_t* __restrict__ state) {
-  const int64_t cnt = *count;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < cnt;
-       t += (int64_t)gridDim.x * 256)
-    state[list[t]] = L_SOLVED;
+__global__ void lzero3_kernel(int64_t* c) {
+  if (threadIdx.x < 3) c[threadIdx.x] = 0;
 }
 
-// start of a round: counters and the pending count
-__global__ void lround_zero_kernel(int32_t* counters, int64_t* npend) {
-  if (threadIdx.x < 2) counters[threadIdx.x] = 0;
-  if (threadIdx.x == 0) *npend = 0;
-}
-
-__global__ __launch_bounds__(256) void lowner_kernel(
-    const uint32_t* __restrict__ pred, const int64_t* __restrict__ start,
-    const uint64_t* __restrict__ acc, const int32_t* __restrict__ state,
-    int64_t N, int32_t* __restrict__ owner, int32_t* __restrict__ is_center) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
-  const int32_t s = state[j];
-  int32_t o = -1;
-  if (s == L_SOLVED) {
-    o = (int32_t)j;
-  } else if (s == L_COVERED) {
-    o = INT32_MAX;
-    for (int64_t t = start[j]; t < start[j + 1]; ++t) {
-      const uint32_t e = pred[t];
-      const int32_t c = (int32_t)(e & 0x1FFFFFFu);
-      if (state[c] == L_SOLVED && kept(acc, e) && c < o) o = c;
-    }
-  }
-  owner[j] = o;
-  is_center[j] = s == L_SOLVED;
+__global__ void lzero1_kernel(int64_t* c) {
+  if (threadIdx.x == 0) *c = 0;
 }
 
 __global__ __launch_bounds__(256) void lzero_kernel(int32_t* p, int64_t n) {
@@ -151,78 +186,92 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
     return fail(ctx, ORBF_EINVAL, "Lebesgue covering: N < 2^25, n <= 128");
   orbf_status st = ORBF_OK;
   auto* ball = (uint64_t*)scratch(ctx, B_BALL, (size_t)N * 16, &st);
-  auto* indeg = (int32_t*)scratch(ctx, B_INDEG, (size_t)(N + 1) * 4, &st);
-  auto* pstart = (int64_t*)scratch(ctx, B_PRED_START, (size_t)(N + 2) * 8, &st);
-  auto* fill = (int32_t*)scratch(ctx, B_PRED_FILL, (size_t)(N + 1) * 4, &st);
+  auto* open = (int32_t*)scratch(ctx, B_INDEG, (size_t)(N + 1) * 4, &st);
   auto* state = (int32_t*)scratch(ctx, B_STATE, (size_t)N * 4, &st);
   auto* flag = (int32_t*)scratch(ctx, B_FLAGS, (size_t)(N + 1) * 4, &st);
   auto* pos = (int64_t*)scratch(ctx, B_CENTER_POS, (size_t)(N + 2) * 8, &st);
-  auto* list = (int32_t*)scratch(ctx, B_ROWPTR_TMP, (size_t)(N + 1) * 4, &st);
+  auto* lists = (int32_t*)scratch(ctx, B_PRED, (size_t)(N + 1) * 12, &st);
   auto* acc = (uint64_t*)scratch(ctx, B_W_TMP, (size_t)N * 16, &st);
-  auto* misc = (int64_t*)scratch(ctx, B_MISC2, 64, &st);
+  auto* cnt = (int64_t*)scratch(ctx, B_MISC2, 64, &st);
   if (st) return st;
-  const size_t max_edges = (size_t)N * (size_t)(n > 1 ? n - 1 : 1);
-  auto* pred = (uint32_t*)scratch(ctx, B_PRED, max_edges * 4, &st);
-  if (st) return st;
+  int32_t* list[3] = {lists, lists + (N + 1), lists + 2 * (N + 1)};
   hipStream_t s = ctx->stream;
   const unsigned g = (unsigned)((N + 255) / 256);
   const unsigned g1 = (unsigned)((N + 256) / 256);
   const unsigned gz = g1 < 65535 ? g1 : 65535;
-  int32_t* counters = (int32_t*)misc;   // 2 int32
-  int64_t* npend = misc + 1;
-  hipLaunchKernelGGL(lzero_kernel, dim3(gz), dim3(256), 0, s, indeg, N + 1);
-  hipLaunchKernelGGL(lzero_kernel, dim3(gz), dim3(256), 0, s, fill, N + 1);
-  hipLaunchKernelGGL(lzero_kernel, dim3(gz), dim3(256), 0, s, (int32_t*)acc,
-                     4 * N);
-  launch_ball(ctx, P0.xyz, P0.knn, P0.rho2, N, d, n, t2, eligible, ball,
-              indeg, state, L_UNDECIDED, L_INELIGIBLE);
-  if ((st = exclusive_scan_i32_to_i64(ctx, indeg, N, pstart))) return st;
-  hipLaunchKernelGGL(lpred_kernel, dim3(g), dim3(256), 0, s, P0.knn, N, n,
-                     ball, pstart, fill, pred);
+  hipLaunchKernelGGL(lzero_kernel, dim3(gz), dim3(256), 0, s, open, N + 1);
+  // acceptance words need no clearing: a center's are written by its solve
+  // before its propagation reads them, and nothing else reads them
+  hipLaunchKernelGGL(lzero3_kernel, dim3(1), dim3(64), 0, s, cnt);
+  launch_ball(ctx, P0.xyz, P0.knn, P0.rho2, N, d, n, t2, eligible, ball, open,
+              state, L_UNDECIDED, L_INELIGIBLE);
+  hipLaunchKernelGGL(lseed_kernel, dim3(g), dim3(256), 0, s, open, N, state,
+                     owner, list[0], cnt);
 
   WeightsParams P = P0;
   P.eligible = eligible;
   P.t2 = t2;
   P.ball = ball;
   P.accept = acc;
-  P.centers = list;
-  P.n_centers = npend;
   P.owner = nullptr;
   P.W = nullptr;
   P.lebesgue = nullptr;
-  // A round decides every node whose predecessors are settled, then solves
-  // the new centers in accept mode and marks them solved.  The kernels read
-  // the pending count on the device, so rounds run back to back and the
-  // host reads the last round's counters only after each batch of rounds;
-  // rounds after the last decision find nothing to do.
+  // Level k propagates list k % 3 into list (k + 1) % 3 and clears the
+  // count of list (k + 2) % 3, which level k - 1 has finished with and
+  // level k + 1 fills.  Until the speculative solve, level k first solves
+  // its list.  The kernels read the counts on the device, so levels run
+  // back to back; the host reads the next level's count only after each
+  // batch of levels, and levels past the last find nothing to do.
   const unsigned gs = (unsigned)(N < kSolveGrid ? N : kSolveGrid);
-  const unsigned gm = (unsigned)((N + 255) / 256 < 1024 ? (N + 255) / 256 : 1024);
-  int32_t hc[2];
-  int64_t rounds = 0;
-  for (int batch = 1;; batch = batch < 64 ? 2 * batch : 64) {
-    for (int r = 0; r < batch; ++r, ++rounds) {
-      hipLaunchKernelGGL(lround_zero_kernel, dim3(1), dim3(64), 0, s,
-                         counters, npend);
-      hipLaunchKernelGGL(ldecide_kernel, dim3(g), dim3(256), 0, s, pred,
-                         pstart, acc, N, state, counters, list, npend);
-      if (!launch_weights_reg(ctx, P, gs))
-        return fail(ctx, ORBF_EINVAL,
-                    "Lebesgue covering needs the register weights kernel "
-                    "(n + M <= 72, M <= 35)");
-      hipLaunchKernelGGL(lsolved_kernel, dim3(gm), dim3(256), 0, s, list,
-                         npend, state);
+  const unsigned gp = (unsigned)((N + 3) / 4 < kPropBlocks ? (N + 3) / 4
+                                                            : kPropBlocks);
+  int64_t level = 0;
+  bool solving = true;
+  auto solve = [&](int32_t* l, int64_t* c) -> orbf_status {
+    P.centers = l;
+    P.n_centers = c;
+    if (!launch_weights_reg(ctx, P, gs))
+      return fail(ctx, ORBF_EINVAL,
+                  "Lebesgue covering needs the register weights kernel "
+                  "(n + M <= 72, M <= 35)");
+    return ORBF_OK;
+  };
+  // while solving, the host checks after every level; then after batches
+  // of 1, 2, 4, ... 64 levels
+  int batch = 1;
+  for (;;) {
+    for (int r = 0; r < batch; ++r, ++level) {
+      const int a = (int)(level % 3), b = (a + 1) % 3, z = (a + 2) % 3;
+      if (solving && (st = solve(list[a], cnt + a))) return st;
+      hipLaunchKernelGGL(lprop_kernel, dim3(gp), dim3(256), 0, s, list[a],
+                         cnt + a, P0.knn, n, ball, acc, open, state, owner,
+                         list[b], cnt + b, cnt + z);
     }
-    hipError_t e = hipMemcpyAsync(hc, counters, sizeof hc,
+    int64_t next = 0;
+    hipError_t e = hipMemcpyAsync(&next, cnt + (int)(level % 3), sizeof next,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if ((st = hip_check(ctx, e, "Lebesgue covering round"))) return st;
-    // the last round left no node undecided and made no new center
-    if (hc[0] == 0 && hc[1] == 0) break;
-    if (rounds > N + 2)
+    if ((st = hip_check(ctx, e, "Lebesgue covering level"))) return st;
+    if (next == 0) break;
+    if (level > N + 2)
       return fail(ctx, ORBF_EINTERNAL, "Lebesgue covering did not settle");
+    if (solving && level >= kSolvedLevels) {
+      // the DAG is deep: solve the next level's centers and every node
+      // still undecided now, then settle the rest without solves
+      const int a = (int)(level % 3), z = (a + 2) % 3;
+      if ((st = solve(list[a], cnt + a))) return st;
+      hipLaunchKernelGGL(lzero1_kernel, dim3(1), dim3(64), 0, s, cnt + z);
+      hipLaunchKernelGGL(lspec_kernel, dim3(g), dim3(256), 0, s, state, ball,
+                         N, list[z], cnt + z);
+      if ((st = solve(list[z], cnt + z))) return st;
+      hipLaunchKernelGGL(lzero1_kernel, dim3(1), dim3(64), 0, s, cnt + z);
+      solving = false;
+      continue;  // the next batch is one level
+    }
+    if (!solving) batch = batch < 64 ? 2 * batch : 64;
   }
-  hipLaunchKernelGGL(lowner_kernel, dim3(g), dim3(256), 0, s, pred, pstart,
-                     acc, state, N, owner, flag);
+  hipLaunchKernelGGL(lfinal_kernel, dim3(g), dim3(256), 0, s, state, N, owner,
+                     flag, ctx->status);
   if ((st = exclusive_scan_i32_to_i64(ctx, flag, N, pos))) return st;
   hipLaunchKernelGGL(lcompact_kernel, dim3(g1), dim3(256), 0, s, flag, pos, N,
                      centers, n_centers);

@@ -95,6 +95,16 @@ CASES = {
                              delta=0.5),
     "ball20k_unaug_d03": dict(kind="ball", N=20000, n=50, m=3, l=-1,
                               delta=0.3),
+    # spatially ordered inputs make the Lebesgue covering's DAG deep (about
+    # a hundred levels): past the first levels the remaining nodes are
+    # solved speculatively and the DAG settles by propagation alone
+    "disk20k_gen_d05_tau5": dict(kind="disk", N=20000, n=31, m=5, l=4,
+                                 delta=0.5, tau=5.0, order="generation"),
+    "disk20k_gen_d03_tau1_prefix": dict(kind="disk", N=20000, n=31, m=5,
+                                        l=4, delta=0.3, tau=1.0,
+                                        order="generation", prefix=True),
+    "ball20k_lex_d03_tau2": dict(kind="ball_lex", N=20000, n=50, m=5, l=3,
+                                 delta=0.3, tau=2.0),
 }
 
 
@@ -104,7 +114,8 @@ def make(case):
     if c["kind"] == "square":
         x = nodesets.square(45, 0)
     elif c["kind"] in ("disk", "disk_refined"):
-        D = nodesets.disk(c["N"], 200, 1, refine=c["kind"] == "disk_refined")
+        D = nodesets.disk(c["N"], 200, 1, refine=c["kind"] == "disk_refined",
+                          order=c.get("order", "shuffled"))
         x, el, bnd, nrm = D["x"], D["eligible"], D["boundary"], D["normals"]
     else:
         x = nodesets.ball(c["N"], 2)["x"]
@@ -158,13 +169,16 @@ def test_build_dm_matches_oracle(orbf, ctx, case):
     assert np.allclose(lam[rows], np.abs(ref["W"][rows]).sum(1), rtol=1e-8)
 
 
-def test_disk_full_size(orbf, ctx):
+@pytest.mark.parametrize("order", ["shuffled", "generation"])
+def test_disk_full_size(orbf, ctx, order):
     """2D disk, 99,400 interior + 600 boundary nodes, n = 31, l = 4, r^5,
     delta = 0.5, Lebesgue threshold 5, Laplacian interior rows +
-    normal-derivative boundary rows: the whole DM against the oracle."""
-    D = nodesets.disk(99400, 600, 1)
+    normal-derivative boundary rows: the whole DM against the oracle, in a
+    scattered numbering and in the Poisson-disk generation order (a DAG
+    about two hundred levels deep)."""
+    D = nodesets.disk(99400, 600, 1, order=order)
     x = D["x"]
-    _say(f"[gpu] disk full N={len(x)}")
+    _say(f"[gpu] disk full N={len(x)} order={order}")
     ref = oracle.build_dm(x, 31, 5, 4, 0.5, tau=5.0, eligible=D["eligible"],
                           boundary=D["boundary"], normals=D["normals"])
     _say(f"[gpu] disk full: oracle Lebesgue margin {ref['min_margin']:.2e}")
