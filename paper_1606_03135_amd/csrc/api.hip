@@ -179,6 +179,7 @@ void orbf_destroy(orbf_ctx* ctx) {
   if (ctx->status_host) hipHostFree(ctx->status_host);
   if (ctx->host_counter) hipHostFree(ctx->host_counter);
   if (ctx->host_scalars) hipHostFree(ctx->host_scalars);
+  if (ctx->cover_tab_host) hipHostFree(ctx->cover_tab_host);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);
   if (ctx->owns_stream && ctx->stream) hipStreamDestroy(ctx->stream);

@@ -40,17 +40,8 @@ static int monomials(int d, int l) {
   return (int)(num / den);
 }
 
-// The whole single-set path on context c (asynchronous on c->stream).
-orbf_status build_set(orbf_ctx* c, const orbf_set_desc& s) {
-  orbf_status st =
-      orbf_build_nodes_knn(c, s.xyz, s.N, s.d, s.n, s.knn, s.rho2);
-  if (st) return st;
-  if (isinf(s.tau)) {
-    st = orbf_select_overlapped_stencils(c, s.xyz, s.knn, s.rho2, s.N, s.d,
-                                         s.n, s.delta, s.eligible, s.centers,
-                                         s.n_centers, s.owner, nullptr);
-    if (st) return st;
-  }
+// The single-set path after the covering: weights, boundary rows, CSR.
+static orbf_status build_after_cover(orbf_ctx* c, const orbf_set_desc& s) {
   orbf_weights_args a;
   memset(&a, 0, sizeof a);
   a.xyz = s.xyz;
@@ -67,7 +58,8 @@ orbf_status build_set(orbf_ctx* c, const orbf_set_desc& s) {
   a.W = s.W;
   a.lebesgue = s.lebesgue;
   a.ir_steps = s.ir_steps;
-  st = orbf_compute_weights(c, ORBF_OP_LAPLACIAN, s.m, s.l, s.n, s.delta, &a);
+  orbf_status st =
+      orbf_compute_weights(c, ORBF_OP_LAPLACIAN, s.m, s.l, s.n, s.delta, &a);
   if (st) return st;
   if (s.boundary && s.n_boundary > 0) {
     orbf_weights_args b = a;
@@ -83,6 +75,20 @@ orbf_status build_set(orbf_ctx* c, const orbf_set_desc& s) {
   }
   return orbf_assemble_csr(c, s.N, s.n, s.knn, s.owner, s.W, s.row_ptr,
                            s.col, s.val);
+}
+
+// The whole single-set path on context c (asynchronous on c->stream).
+orbf_status build_set(orbf_ctx* c, const orbf_set_desc& s) {
+  orbf_status st =
+      orbf_build_nodes_knn(c, s.xyz, s.N, s.d, s.n, s.knn, s.rho2);
+  if (st) return st;
+  if (isinf(s.tau)) {
+    st = orbf_select_overlapped_stencils(c, s.xyz, s.knn, s.rho2, s.N, s.d,
+                                         s.n, s.delta, s.eligible, s.centers,
+                                         s.n_centers, s.owner, nullptr);
+    if (st) return st;
+  }
+  return build_after_cover(c, s);
 }
 
 // Host-side checks of one set (the entry points check again).
@@ -169,9 +175,128 @@ orbf_status ensure_workers(orbf_ctx* ctx, int want) {
   return ORBF_OK;
 }
 
+// Enqueue a batch whose sets all have tau = INFINITY with the coverings'
+// levels shared: (1) per worker, each set's kNN, ball masks and seeds,
+// into per-node arrays numbered globally across the batch; (2) on `origin`,
+// the covering levels of all sets at once, so the number of level launches
+// is the deepest set's depth rather than the sum over sets; (3) per worker,
+// each set's center list, weights, boundary rows and CSR.  Every step of a
+// set reads and writes only that set's slice of the shared arrays, so its
+// result is the same as alone.  Sets *no_room (with nothing enqueued) if
+// the shared arrays do not fit the context's budget.
+static orbf_status enqueue_batch_shared(
+    orbf_ctx* ctx, const orbf_set_desc* sets, int nsets, int nw,
+    hipStream_t origin, const std::vector<std::vector<int>>& plan,
+    bool* no_room) {
+  *no_room = false;
+  // the shared arrays reuse this context's scratch (B_PERM among them), so
+  // its caches of an earlier single-set call are no longer valid
+  ctx->d2_cache = D2Cache();
+  ctx->p_cache = PCache();
+  std::vector<int64_t> base(nsets);
+  int64_t total = 0;
+  for (int i = 0; i < nsets; ++i) {
+    base[i] = total;
+    total += sets[i].N;
+  }
+  if (total >= INT32_MAX) {
+    *no_room = true;
+    return ORBF_OK;
+  }
+  orbf_status st = ORBF_OK;
+  MultiCover mc;
+  mc.ball = (uint64_t*)scratch(ctx, B_BALL, (size_t)total * 16, &st);
+  mc.cnt = (int32_t*)scratch(ctx, B_INDEG, (size_t)(total + 1) * 4, &st);
+  mc.state = (int32_t*)scratch(ctx, B_STATE, (size_t)(total + 1) * 4, &st);
+  mc.flag = (int32_t*)scratch(ctx, B_FLAGS, (size_t)(total + 1) * 4, &st);
+  mc.setid = (int32_t*)scratch(ctx, B_PERM, (size_t)(total + 1) * 4, &st);
+  mc.q0 = (int32_t*)scratch(ctx, B_PRED_FILL, (size_t)(total + 1) * 4, &st);
+  mc.q1 = (int32_t*)scratch(ctx, B_ROWPTR_TMP, (size_t)(total + 1) * 4, &st);
+  mc.qc = (int32_t*)scratch(ctx, B_MISC2, 64, &st);
+  auto* tab = (CoverSet*)scratch(ctx, B_CLASS,
+                                 sizeof(CoverSet) * (size_t)nsets, &st);
+  if (st == ORBF_EBUDGET) {
+    *no_room = true;
+    ctx->err.clear();
+    return ORBF_OK;
+  }
+  if (st) return st;
+  mc.tab = tab;
+  mc.total = total;
+  mc.key = sets[0].knn;
+  const size_t tb = sizeof(CoverSet) * (size_t)nsets;
+  if (ctx->cover_tab_cap < tb) {
+    if (ctx->cover_tab_host) hipHostFree(ctx->cover_tab_host);
+    ctx->cover_tab_host = nullptr;
+    ctx->cover_tab_cap = 0;
+    hipError_t e = hipHostMalloc(&ctx->cover_tab_host, tb,
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) return hip_check(ctx, e, "batch set table");
+    ctx->cover_tab_cap = tb;
+  }
+  auto* th = (CoverSet*)ctx->cover_tab_host;
+  for (int i = 0; i < nsets; ++i)
+    th[i] = CoverSet{sets[i].knn, sets[i].owner, base[i], sets[i].n};
+  hipError_t e =
+      hipMemcpyAsync(tab, th, tb, hipMemcpyHostToDevice, origin);
+  if (e != hipSuccess) return hip_check(ctx, e, "batch set table copy");
+  cover_multi_reset(mc, origin);
+
+  auto fork = [&]() -> orbf_status {
+    hipError_t e2 = hipEventRecord(ctx->fork_ev, origin);
+    if (e2 != hipSuccess) return hip_check(ctx, e2, "batch fork");
+    for (int w = 0; w < nw; ++w) {
+      e2 = hipStreamWaitEvent(ctx->workers[w]->stream, ctx->fork_ev, 0);
+      if (e2 != hipSuccess) return hip_check(ctx, e2, "batch fork wait");
+    }
+    return ORBF_OK;
+  };
+  auto join = [&]() -> orbf_status {
+    for (int w = 0; w < nw; ++w) {
+      hipError_t e2 = hipEventRecord(ctx->join_ev[w], ctx->workers[w]->stream);
+      if (e2 != hipSuccess) return hip_check(ctx, e2, "batch join");
+      e2 = hipStreamWaitEvent(origin, ctx->join_ev[w], 0);
+      if (e2 != hipSuccess) return hip_check(ctx, e2, "batch join wait");
+    }
+    return ORBF_OK;
+  };
+  auto set_fail = [&](int i, orbf_ctx* wc, orbf_status code) {
+    return fail(ctx, code, "set " + std::to_string(i) + ": " + wc->err);
+  };
+  if ((st = fork())) return st;
+  for (int w = 0; w < nw; ++w) {
+    orbf_ctx* wc = ctx->workers[w];
+    for (int i : plan[w]) {
+      const orbf_set_desc& s = sets[i];
+      st = orbf_build_nodes_knn(wc, s.xyz, s.N, s.d, s.n, s.knn, s.rho2);
+      if (st) return set_fail(i, wc, st);
+      const double t = 1.0 - s.delta;
+      st = cover_multi_prologue(wc, s.xyz, s.knn, s.rho2, s.N, s.d, s.n,
+                                t * t, s.eligible, s.owner, mc, base[i], i);
+      if (st) return set_fail(i, wc, st);
+    }
+  }
+  if ((st = join())) return st;
+  if ((st = cover_multi_levels(ctx, mc, origin))) return st;
+  if ((st = fork())) return st;
+  for (int w = 0; w < nw; ++w) {
+    orbf_ctx* wc = ctx->workers[w];
+    for (int i : plan[w]) {
+      const orbf_set_desc& s = sets[i];
+      st = cover_multi_epilogue(wc, s.knn, s.N, s.n, s.owner, s.centers,
+                                s.n_centers, mc, base[i]);
+      if (st) return set_fail(i, wc, st);
+      st = build_after_cover(wc, s);
+      if (st) return set_fail(i, wc, st);
+    }
+  }
+  return join();
+}
+
 // Enqueue the batch on `origin`: fork, per-worker set lists, join.
 static orbf_status enqueue_batch(orbf_ctx* ctx, const orbf_set_desc* sets,
-                                 int nsets, int nw, hipStream_t origin) {
+                                 int nsets, int nw, hipStream_t origin,
+                                 bool shared) {
   std::vector<int> order(nsets);
   std::vector<double> cost(nsets);
   for (int i = 0; i < nsets; ++i) {
@@ -192,6 +317,13 @@ static orbf_status enqueue_batch(orbf_ctx* ctx, const orbf_set_desc* sets,
   for (int w = 0; w < nw; ++w) {
     ctx->workers[w]->schedules = ctx->schedules;
     ctx->workers[w]->ir_max_corrections = ctx->ir_max_corrections;
+  }
+  if (shared) {
+    bool no_room = false;
+    const orbf_status st =
+        enqueue_batch_shared(ctx, sets, nsets, nw, origin, plan, &no_room);
+    // without room for the shared arrays, the sets go one by one
+    if (st || !no_room) return st;
   }
   hipError_t e = hipEventRecord(ctx->fork_ev, origin);
   if (e != hipSuccess) return hip_check(ctx, e, "batch fork");
@@ -274,7 +406,7 @@ orbf_status orbf_build_dm_batched(orbf_ctx* ctx, const orbf_set_desc* sets,
     e = hipStreamBeginCapture(ctx->cap_stream,
                               hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_check(ctx, e, "batch capture");
-    st = enqueue_batch(ctx, sets, nsets, nw, ctx->cap_stream);
+    st = enqueue_batch(ctx, sets, nsets, nw, ctx->cap_stream, all_inf);
     hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
     if (st || e2 != hipSuccess) {
       if (g) hipGraphDestroy(g);
@@ -298,7 +430,7 @@ orbf_status orbf_build_dm_batched(orbf_ctx* ctx, const orbf_set_desc* sets,
     memcpy(ctx->graph_key.data() + kbytes, &nw, sizeof(int));
     ctx->graph_seen = 1;
   }
-  return enqueue_batch(ctx, sets, nsets, nw, ctx->stream);
+  return enqueue_batch(ctx, sets, nsets, nw, ctx->stream, all_inf);
 }
 
 }  // extern "C"

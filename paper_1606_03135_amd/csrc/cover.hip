@@ -190,7 +190,7 @@ constexpr int32_t kCenterBit = INT32_MIN;  // stack/queue entry: center flag
 __global__ __launch_bounds__(256) void seed_kernel(
     const int32_t* __restrict__ cnt, int64_t N, int32_t* state,
     int32_t* __restrict__ owner, int32_t* __restrict__ is_center,
-    int32_t* __restrict__ q, int32_t* qn) {
+    int32_t* __restrict__ q, int32_t* qn, int64_t base) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= N) return;
   const bool open = state[j] == S_UNDECIDED;
@@ -202,30 +202,38 @@ __global__ __launch_bounds__(256) void seed_kernel(
     const uint64_t m = __ballot(true);  // the seeding lanes of this wave
     const int lane = (int)(threadIdx.x & 63);
     const int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(qn, (int)__popcll(m));
-    base = __shfl(base, leader, 64);
-    q[base + (int)__popcll(m & ((1ull << lane) - 1))] =
-        (int32_t)j | kCenterBit;
+    int at = 0;
+    if (lane == leader) at = atomicAdd(qn, (int)__popcll(m));
+    at = __shfl(at, leader, 64);
+    q[at + (int)__popcll(m & ((1ull << lane) - 1))] =
+        (int32_t)(j + base) | kCenterBit;
   }
 }
 
 // Process one queue entry (and what the group follows) with the sixteen
-// lanes of a group; control flow is uniform over the group.
+// lanes of a group; control flow is uniform over the group.  Queue entries
+// and the per-node arrays (ball, cnt, state, is_center) use global node
+// numbers: node j of a set is base + j.  MULTI: the set of a node comes
+// from `setid` and its table row; otherwise every node is in `one`.
+template <bool MULTI>
 __device__ __forceinline__ void process_entry(
-    int32_t entry, int32_t* stk, const int32_t* __restrict__ knn,
-    const uint64_t* __restrict__ ball, int n, int32_t* cnt, int32_t* state,
-    int32_t* owner, int32_t* __restrict__ is_center,
-    int32_t* __restrict__ qnext, int32_t* qn, int follow) {
+    int32_t entry, int32_t* stk, const CoverSet& one,
+    const CoverSet* __restrict__ tab, const int32_t* __restrict__ setid,
+    const uint64_t* __restrict__ ball, int32_t* cnt, int32_t* state,
+    int32_t* __restrict__ is_center, int32_t* __restrict__ qnext, int32_t* qn,
+    int follow) {
   const int lane = (int)(threadIdx.x & 63), pl = lane & 15;
   const int gshift = lane & 48;  // first lane of the group in the wave
   const uint32_t below = (1u << pl) - 1u;
   int sp = 0;
   int32_t e = entry;
   for (;;) {
-    const int32_t c = e & INT32_MAX;
+    const int32_t g = e & INT32_MAX;
     const bool center = e < 0;
-    const uint64_t b0 = ball[2 * (int64_t)c], b1 = ball[2 * (int64_t)c + 1];
+    const CoverSet T = MULTI ? tab[setid[g]] : one;
+    const int32_t c = (int32_t)(g - T.base);
+    const int n = T.n;
+    const uint64_t b0 = ball[2 * (int64_t)g], b1 = ball[2 * (int64_t)g + 1];
     int32_t dec[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -233,16 +241,17 @@ __device__ __forceinline__ void process_entry(
       dec[i] = -1;
       const uint64_t bits = q < 64 ? b0 : b1;
       if (q < n && ((bits >> (q & 63)) & 1ull)) {
-        const int32_t j = knn[(int64_t)c * n + q];
+        const int32_t j = T.knn[(int64_t)c * n + q];
+        const int32_t jg = (int32_t)(T.base + j);
         if (center) {
-          atomicMin(&owner[j], c);
-          if (atomicCAS(&state[j], S_UNDECIDED, S_COVERED) == S_UNDECIDED)
-            dec[i] = j;
-        } else if (atomicSub(&cnt[j], 1) == 1) {
-          __atomic_store_n(&state[j], S_CENTER, __ATOMIC_RELAXED);
-          owner[j] = j;
-          is_center[j] = 1;
-          dec[i] = j | kCenterBit;
+          atomicMin(&T.owner[j], c);
+          if (atomicCAS(&state[jg], S_UNDECIDED, S_COVERED) == S_UNDECIDED)
+            dec[i] = jg;
+        } else if (atomicSub(&cnt[jg], 1) == 1) {
+          __atomic_store_n(&state[jg], S_CENTER, __ATOMIC_RELAXED);
+          T.owner[j] = j;
+          is_center[jg] = 1;
+          dec[i] = jg | kCenterBit;
         }
       }
     }
@@ -282,11 +291,13 @@ __device__ __forceinline__ void process_entry(
 // sixteen lanes per entry; decisions that are not followed go to the other
 // queue (count qc[(lv+1) % 3]); qc[(lv+2) % 3], read by the previous level,
 // is cleared for the next.
+template <bool MULTI>
 __global__ __launch_bounds__(256) void level_kernel(
-    const int32_t* __restrict__ knn, const uint64_t* __restrict__ ball,
-    int n, int32_t* cnt, int32_t* state, int32_t* owner,
-    int32_t* __restrict__ is_center, int32_t* __restrict__ q0,
-    int32_t* __restrict__ q1, int32_t* qc, int lv, int follow) {
+    CoverSet one, const CoverSet* __restrict__ tab,
+    const int32_t* __restrict__ setid, const uint64_t* __restrict__ ball,
+    int32_t* cnt, int32_t* state, int32_t* __restrict__ is_center,
+    int32_t* __restrict__ q0, int32_t* __restrict__ q1, int32_t* qc, int lv,
+    int follow) {
   __shared__ int32_t stk[16 * kStack];
   const int32_t count = qc[lv % 3];
   if (blockIdx.x == 0 && threadIdx.x == 0) qc[(lv + 2) % 3] = 0;
@@ -296,17 +307,18 @@ __global__ __launch_bounds__(256) void level_kernel(
   const int grp = threadIdx.x >> 4;
   for (int64_t t = (int64_t)blockIdx.x * 16 + grp; t < count;
        t += (int64_t)gridDim.x * 16)
-    process_entry(cur[t], stk + grp * kStack, knn, ball, n, cnt, state,
-                  owner, is_center, nxt, qn, follow);
+    process_entry<MULTI>(cur[t], stk + grp * kStack, one, tab, setid, ball,
+                         cnt, state, is_center, nxt, qn, follow);
 }
 
 // One workgroup runs the remaining levels from `lv` until a queue is empty.
 // Every node enters a queue at most once, so at most N + 1 levels remain.
+template <bool MULTI>
 __global__ __launch_bounds__(256) void finish_levels_kernel(
-    const int32_t* __restrict__ knn, const uint64_t* __restrict__ ball,
-    int n, int64_t N, int32_t* cnt, int32_t* state, int32_t* owner,
-    int32_t* __restrict__ is_center, int32_t* __restrict__ q0,
-    int32_t* __restrict__ q1, int32_t* qc, int lv) {
+    CoverSet one, const CoverSet* __restrict__ tab,
+    const int32_t* __restrict__ setid, const uint64_t* __restrict__ ball,
+    int64_t N, int32_t* cnt, int32_t* state, int32_t* __restrict__ is_center,
+    int32_t* __restrict__ q0, int32_t* __restrict__ q1, int32_t* qc, int lv) {
   __shared__ int32_t stk[16 * kStack];
   __shared__ int32_t count;
   const int grp = threadIdx.x >> 4;
@@ -321,10 +333,18 @@ __global__ __launch_bounds__(256) void finish_levels_kernel(
     const int32_t* cur = (lv & 1) ? q1 : q0;
     int32_t* nxt = (lv & 1) ? q0 : q1;
     for (int t = grp; t < count; t += 16)
-      process_entry(cur[t], stk + grp * kStack, knn, ball, n, cnt, state,
-                    owner, is_center, nxt, &qc[(lv + 1) % 3], kFollowDeep);
+      process_entry<MULTI>(cur[t], stk + grp * kStack, one, tab, setid, ball,
+                           cnt, state, is_center, nxt, &qc[(lv + 1) % 3],
+                           kFollowDeep);
     __threadfence();
   }
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t n,
+                                                       int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256)
+    p[i] = v;
 }
 
 __global__ void zero3_i32_kernel(int32_t* p) {
@@ -384,49 +404,42 @@ void launch_ball(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   }
 }
 
-orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
-                         const double* rho2, int64_t N, int d, int n,
-                         double t2, const uint8_t* eligible, int32_t* centers,
-                         int64_t* n_centers, int32_t* owner, int32_t* p) {
+namespace {
+
+// The levels after the seeds, for one set (tab == nullptr) or many.  The
+// number of levels is the depth of the DAG left after the threads' own
+// chain following, known only on the device.  An eager call launches
+// levels in growing batches and reads the queue length after each batch,
+// and records how many levels it used; a call under graph capture cannot
+// read it and replays the recorded count.  One workgroup then runs whatever
+// levels remain (none, unless a captured call meets a deeper input than
+// the one it recorded).
+orbf_status run_levels(orbf_ctx* ctx, hipStream_t s, const CoverSet& one,
+                       const CoverSet* tab, const int32_t* setid,
+                       uint64_t* ball, int32_t* cnt, int32_t* state,
+                       int32_t* flag, int32_t* q0, int32_t* q1, int32_t* qc,
+                       int64_t N, const void* key_ptr) {
   orbf_status st = ORBF_OK;
-  auto* ball = (uint64_t*)scratch(ctx, B_BALL, (size_t)N * 16, &st);
-  auto* cnt = (int32_t*)scratch(ctx, B_INDEG, (size_t)(N + 1) * 4, &st);
-  auto* q0 = (int32_t*)scratch(ctx, B_PRED_FILL, (size_t)(N + 1) * 4, &st);
-  auto* q1 = (int32_t*)scratch(ctx, B_ROWPTR_TMP, (size_t)(N + 1) * 4, &st);
-  auto* state = (int32_t*)scratch(ctx, B_STATE, (size_t)N * 4, &st);
-  auto* flag = (int32_t*)scratch(ctx, B_FLAGS, (size_t)(N + 1) * 4, &st);
-  auto* pos = (int64_t*)scratch(ctx, B_CENTER_POS, (size_t)(N + 2) * 8, &st);
-  auto* qc = (int32_t*)scratch(ctx, B_MISC2, 64, &st);
-  if (st) return st;
-  hipStream_t s = ctx->stream;
-  const unsigned g = (unsigned)((N + 255) / 256);
-  const unsigned gz = (unsigned)((N + 256) / 256 < 65535 ? (N + 256) / 256 : 65535);
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(gz), dim3(256), 0, s, cnt, N + 1);
-  hipLaunchKernelGGL(zero3_i32_kernel, dim3(1), dim3(64), 0, s, qc);
-  launch_ball(ctx, xyz, knn, rho2, N, d, n, t2, eligible, ball, cnt, state,
-              S_UNDECIDED, S_INELIGIBLE);
-  hipLaunchKernelGGL(seed_kernel, dim3(g), dim3(256), 0, s, cnt, N, state,
-                     owner, flag, q0, qc);
   const int64_t want_blocks = (N + 255) / 256;
   const unsigned gl =
       (unsigned)(want_blocks < kLevelBlocks ? want_blocks : kLevelBlocks);
   int lv = 0;
   auto levels = [&](int k) {
-    for (int r = 0; r < k; ++r, ++lv)
-      hipLaunchKernelGGL(level_kernel, dim3(gl), dim3(256), 0, s, knn, ball,
-                         n, cnt, state, owner, flag, q0, q1, qc, lv,
-                         lv < kWideLevels ? kFollowWide : kFollowDeep);
+    for (int r = 0; r < k; ++r, ++lv) {
+      const int follow = lv < kWideLevels ? kFollowWide : kFollowDeep;
+      if (tab)
+        hipLaunchKernelGGL(level_kernel<true>, dim3(gl), dim3(256), 0, s, one,
+                           tab, setid, ball, cnt, state, flag, q0, q1, qc, lv,
+                           follow);
+      else
+        hipLaunchKernelGGL(level_kernel<false>, dim3(gl), dim3(256), 0, s,
+                           one, tab, setid, ball, cnt, state, flag, q0, q1,
+                           qc, lv, follow);
+    }
   };
-  // The number of levels is the depth of the DAG left after the threads'
-  // own chain following, known only on the device.  An eager call launches
-  // levels in growing batches and reads the queue length after each batch,
-  // and records how many levels it used; a call under graph capture cannot
-  // read it and replays the recorded count.  One workgroup then runs
-  // whatever levels remain (none, unless a captured call meets a deeper
-  // input than the one it recorded).
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   hipStreamIsCapturing(s, &cap);
-  const std::pair<const void*, int64_t> key(knn, N);
+  const std::pair<const void*, int64_t> key(key_ptr, N);
   int recorded = -1;
   for (size_t i = 0; i < ctx->cover_keys.size(); ++i)
     if (ctx->cover_keys[i] == key) recorded = ctx->cover_rounds[i];
@@ -459,8 +472,25 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
       ctx->cover_rounds.push_back(lv);
     }
   }
-  hipLaunchKernelGGL(finish_levels_kernel, dim3(1), dim3(256), 0, s, knn,
-                     ball, n, N, cnt, state, owner, flag, q0, q1, qc, lv);
+  if (tab)
+    hipLaunchKernelGGL(finish_levels_kernel<true>, dim3(1), dim3(256), 0, s,
+                       one, tab, setid, ball, N, cnt, state, flag, q0, q1, qc,
+                       lv);
+  else
+    hipLaunchKernelGGL(finish_levels_kernel<false>, dim3(1), dim3(256), 0, s,
+                       one, tab, setid, ball, N, cnt, state, flag, q0, q1, qc,
+                       lv);
+  return hip_check(ctx, hipGetLastError(), "cover levels");
+}
+
+// center list, p per center, and the context's p cache (flag: is_center)
+orbf_status finish_centers(orbf_ctx* ctx, const int32_t* flag,
+                           const int32_t* knn, const uint64_t* ball,
+                           const int32_t* owner, int64_t N, int n,
+                           int32_t* centers, int64_t* n_centers, int32_t* p) {
+  orbf_status st = ORBF_OK;
+  auto* pos = (int64_t*)scratch(ctx, B_CENTER_POS, (size_t)(N + 2) * 8, &st);
+  if (st) return st;
   st = exclusive_scan_i32_to_i64(ctx, flag, N, pos);
   if (st) return st;
   // the row counts are also kept in the context, for the weights entry
@@ -468,10 +498,82 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   auto* p_keep = (int32_t*)scratch(ctx, B_P_CACHE, (size_t)N * 4, &st);
   if (st) return st;
   hipLaunchKernelGGL(centers_kernel, dim3((unsigned)((N + 256) / 256)),
-                     dim3(256), 0, s, flag, pos, knn, ball, owner, N, n,
-                     centers, p, p_keep, n_centers);
+                     dim3(256), 0, ctx->stream, flag, pos, knn, ball, owner, N,
+                     n, centers, p, p_keep, n_centers);
   ctx->p_cache = {centers, owner, N, n, p_keep};
   return hip_check(ctx, hipGetLastError(), "cover");
+}
+
+}  // namespace
+
+orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
+                         const double* rho2, int64_t N, int d, int n,
+                         double t2, const uint8_t* eligible, int32_t* centers,
+                         int64_t* n_centers, int32_t* owner, int32_t* p) {
+  orbf_status st = ORBF_OK;
+  auto* ball = (uint64_t*)scratch(ctx, B_BALL, (size_t)N * 16, &st);
+  auto* cnt = (int32_t*)scratch(ctx, B_INDEG, (size_t)(N + 1) * 4, &st);
+  auto* q0 = (int32_t*)scratch(ctx, B_PRED_FILL, (size_t)(N + 1) * 4, &st);
+  auto* q1 = (int32_t*)scratch(ctx, B_ROWPTR_TMP, (size_t)(N + 1) * 4, &st);
+  auto* state = (int32_t*)scratch(ctx, B_STATE, (size_t)N * 4, &st);
+  auto* flag = (int32_t*)scratch(ctx, B_FLAGS, (size_t)(N + 1) * 4, &st);
+  auto* qc = (int32_t*)scratch(ctx, B_MISC2, 64, &st);
+  if (st) return st;
+  hipStream_t s = ctx->stream;
+  const unsigned g = (unsigned)((N + 255) / 256);
+  const unsigned gz = (unsigned)((N + 256) / 256 < 65535 ? (N + 256) / 256 : 65535);
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(gz), dim3(256), 0, s, cnt, N + 1);
+  hipLaunchKernelGGL(zero3_i32_kernel, dim3(1), dim3(64), 0, s, qc);
+  launch_ball(ctx, xyz, knn, rho2, N, d, n, t2, eligible, ball, cnt, state,
+              S_UNDECIDED, S_INELIGIBLE);
+  hipLaunchKernelGGL(seed_kernel, dim3(g), dim3(256), 0, s, cnt, N, state,
+                     owner, flag, q0, qc, (int64_t)0);
+  const CoverSet one{knn, owner, 0, n};
+  st = run_levels(ctx, s, one, nullptr, nullptr, ball, cnt, state, flag, q0,
+                  q1, qc, N, knn);
+  if (st) return st;
+  return finish_centers(ctx, flag, knn, ball, owner, N, n, centers, n_centers,
+                        p);
+}
+
+orbf_status cover_multi_prologue(orbf_ctx* w, const double* xyz,
+                                 const int32_t* knn, const double* rho2,
+                                 int64_t N, int d, int n, double t2,
+                                 const uint8_t* eligible, int32_t* owner,
+                                 const MultiCover& mc, int64_t base,
+                                 int32_t set_index) {
+  hipStream_t s = w->stream;
+  const unsigned g = (unsigned)((N + 255) / 256);
+  const unsigned gz = g < 65535 ? g : 65535;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(gz), dim3(256), 0, s,
+                     mc.cnt + base, N);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(gz), dim3(256), 0, s,
+                     mc.setid + base, N, set_index);
+  launch_ball(w, xyz, knn, rho2, N, d, n, t2, eligible, mc.ball + 2 * base,
+              mc.cnt + base, mc.state + base, S_UNDECIDED, S_INELIGIBLE);
+  hipLaunchKernelGGL(seed_kernel, dim3(g), dim3(256), 0, s, mc.cnt + base, N,
+                     mc.state + base, owner, mc.flag + base, mc.q0, mc.qc,
+                     base);
+  return hip_check(w, hipGetLastError(), "batched cover prologue");
+}
+
+orbf_status cover_multi_levels(orbf_ctx* ctx, const MultiCover& mc,
+                               hipStream_t s) {
+  const CoverSet none{nullptr, nullptr, 0, 0};
+  return run_levels(ctx, s, none, mc.tab, mc.setid, mc.ball, mc.cnt,
+                    mc.state, mc.flag, mc.q0, mc.q1, mc.qc, mc.total, mc.key);
+}
+
+void cover_multi_reset(const MultiCover& mc, hipStream_t s) {
+  hipLaunchKernelGGL(zero3_i32_kernel, dim3(1), dim3(64), 0, s, mc.qc);
+}
+
+orbf_status cover_multi_epilogue(orbf_ctx* w, const int32_t* knn, int64_t N,
+                                 int n, const int32_t* owner,
+                                 int32_t* centers, int64_t* n_centers,
+                                 const MultiCover& mc, int64_t base) {
+  return finish_centers(w, mc.flag + base, knn, mc.ball + 2 * base, owner, N,
+                        n, centers, n_centers, nullptr);
 }
 
 }  // namespace orbf

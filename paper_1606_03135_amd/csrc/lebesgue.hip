@@ -236,9 +236,9 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
                   "(n + M <= 72, M <= 35)");
     return ORBF_OK;
   };
-  // while solving, the host checks after every level; then after batches
-  // of 1, 2, 4, ... 64 levels
-  int batch = 1;
+  // The solved levels run back to back and the host checks once after
+  // them; the propagation-only levels after batches of 1, 2, 4, ... 64.
+  int batch = (int)kSolvedLevels;
   for (;;) {
     for (int r = 0; r < batch; ++r, ++level) {
       const int a = (int)(level % 3), b = (a + 1) % 3, z = (a + 2) % 3;
@@ -255,7 +255,7 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
     if (next == 0) break;
     if (level > N + 2)
       return fail(ctx, ORBF_EINTERNAL, "Lebesgue covering did not settle");
-    if (solving && level >= kSolvedLevels) {
+    if (solving) {
       // the DAG is deep: solve the next level's centers and every node
       // still undecided now, then settle the rest without solves
       const int a = (int)(level % 3), z = (a + 2) % 3;
@@ -266,9 +266,10 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
       if ((st = solve(list[z], cnt + z))) return st;
       hipLaunchKernelGGL(lzero1_kernel, dim3(1), dim3(64), 0, s, cnt + z);
       solving = false;
-      continue;  // the next batch is one level
+      batch = 1;
+      continue;
     }
-    if (!solving) batch = batch < 64 ? 2 * batch : 64;
+    batch = batch < 64 ? 2 * batch : 64;
   }
   hipLaunchKernelGGL(lfinal_kernel, dim3(g), dim3(256), 0, s, state, N, owner,
                      flag, ctx->status);

@@ -78,6 +78,31 @@ struct D2Cache {
 // (B_P_CACHE).  The weights entry point uses it, when handed the same
 // centers and owner arrays, to choose each stencil's pass width; a stale
 // count can only choose a slower width, never change a result.
+// One node set of a covering: its stencils, its owner array, and the global
+// number of its node 0 when several sets share the per-node arrays
+struct CoverSet {
+  const int32_t* knn;
+  int32_t* owner;
+  int64_t base;
+  int n;
+};
+
+// Per-node arrays of a covering over many node sets (global numbering),
+// the sets' table on the device, and the shared level queues
+struct MultiCover {
+  uint64_t* ball = nullptr;
+  int32_t* cnt = nullptr;
+  int32_t* state = nullptr;
+  int32_t* flag = nullptr;
+  int32_t* setid = nullptr;
+  int32_t* q0 = nullptr;
+  int32_t* q1 = nullptr;
+  int32_t* qc = nullptr;
+  const CoverSet* tab = nullptr;
+  int64_t total = 0;
+  const void* key = nullptr;  // identifies the batch for the recorded depth
+};
+
 struct PCache {
   const int32_t* centers = nullptr;
   const int32_t* owner = nullptr;
@@ -127,6 +152,10 @@ struct orbf_ctx {
   std::vector<int> schedules;
   int ir_max_corrections = 8;  // FP32 + refinement: cap before FP64 fallback
   void* csr_scratch = nullptr;  // device address of the CSR no-alloc array
+  // batched builds: pinned staging of the node-set table of the shared
+  // covering levels (kept while a captured graph may read it)
+  void* cover_tab_host = nullptr;
+  size_t cover_tab_cap = 0;
   orbf::D2Cache d2_cache;
   orbf::PCache p_cache;
 };
@@ -192,6 +221,23 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
                          const double* rho2, int64_t N, int d, int n,
                          double t2, const uint8_t* eligible, int32_t* centers,
                          int64_t* n_centers, int32_t* owner, int32_t* p);
+// covering of many node sets with shared levels (batched builds): per set
+// on its worker, ball masks and seeds; then all levels at once; then per
+// set its center list
+orbf_status cover_multi_prologue(orbf_ctx* w, const double* xyz,
+                                 const int32_t* knn, const double* rho2,
+                                 int64_t N, int d, int n, double t2,
+                                 const uint8_t* eligible, int32_t* owner,
+                                 const MultiCover& mc, int64_t base,
+                                 int32_t set_index);
+// clears the shared queue counters (before any set's seeds), on stream s
+void cover_multi_reset(const MultiCover& mc, hipStream_t s);
+orbf_status cover_multi_levels(orbf_ctx* ctx, const MultiCover& mc,
+                               hipStream_t s);
+orbf_status cover_multi_epilogue(orbf_ctx* w, const int32_t* knn, int64_t N,
+                                 int n, const int32_t* owner,
+                                 int32_t* centers, int64_t* n_centers,
+                                 const MultiCover& mc, int64_t base);
 orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
                            double t2, const orbf_weights_args* a);
 orbf_status launch_spmv(orbf_ctx* ctx, int64_t N, const int64_t* row_ptr,
