@@ -665,6 +665,32 @@ def bench_serving(args, torch, orbf, nodesets):
     }
 
 
+def weights_only(args, torch, orbf, nodesets):
+    """The headline ball's weights phase alone, twice, in one precision:
+    the launches a counter run (rocprofv3 --pmc) attributes to the weights
+    kernels, without the rest of the bench."""
+    n, m, l, delta = 50, 5, 3, 0.3
+    x = nodesets.ball(args.N, 2)["x"]
+    xd = torch.from_numpy(x).to("cuda:0")
+    ctx = orbf.Context(0)
+    knn, rho2 = orbf.build_nodes_knn(ctx, xd, n)
+    centers, nc, owner, _ = orbf.select_overlapped_stencils(ctx, xd, knn,
+                                                            rho2, delta)
+    W = torch.empty((len(x), n), dtype=torch.float64, device="cuda:0")
+    prec = orbf.PREC_FP32_IR if args.weights_only == "fp32" else \
+        orbf.PREC_FP64
+    st = torch.empty(len(x), dtype=torch.int32, device="cuda:0")
+    for _ in range(2):
+        orbf.compute_weights(ctx, orbf.OP_LAPLACIAN, m, l, n, delta, xd, knn,
+                             rho2, centers=centers, n_centers=nc,
+                             owner=owner, W=W, prec=prec,
+                             ir_steps=st if prec == orbf.PREC_FP32_IR
+                             else None)
+    ctx.sync()
+    _log(f"weights only, {args.weights_only}: {int(nc.item())} stencils, "
+         "two builds")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -693,6 +719,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run a plain device copy of "
                          "known size (to scale HBM byte counters)")
+    ap.add_argument("--weights-only", choices=["fp64", "fp32"],
+                    help="for counter runs: build the ball's stencils and "
+                         "covering, then run only the weights entry point "
+                         "twice in this precision, and print no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
@@ -704,6 +734,9 @@ def main():
     import nodesets
     import paper_1606_03135_amd as orbf
 
+    if args.weights_only:
+        weights_only(args, torch, orbf, nodesets)
+        return
     fn = {"ball": bench_ball, "batched": bench_batched,
           "serving": bench_serving}[args.workload]
     out = fn(args, torch, orbf, nodesets)

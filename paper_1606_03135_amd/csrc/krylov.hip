@@ -13,15 +13,15 @@
 //   - BiCGSTAB (van der Vorst, 1992);
 //   - GMRES(m) with classical Gram-Schmidt applied twice, Givens rotations
 //     on the host and restarts after m steps.
-// A
-// normal-derivative row scales like 1/h and an interior row like
+// A normal-derivative row scales like 1/h and an interior row like
 // 1 + dt |L_ee|: on Neumann steps Jacobi cuts the iterations 2-3x, on
 // Dirichlet and all-interior steps it costs iterations (disk at dt = 1e-2:
-// 75 -> 98; the 1M-node ball step: 7 -> 12), so the caller chooses.  Products with A
-// use sixteen lanes per row; every inner product is summed in a fixed
-// order (per-block partials, then one wavefront), so a solve is
-// deterministic.  The host drives the iteration and reads each inner
-// product back (pinned memory), four times per iteration.
+// 75 -> 98; the 1M-node ball step: 7 -> 12), so the caller chooses.
+// Products with A use sixteen lanes per row; every inner product is summed
+// in a fixed order (per-block partials, then one wavefront), so a solve is
+// deterministic.  The host drives the iteration and reads the inner
+// products back through pinned memory: four times per BiCGSTAB iteration,
+// once per GMRES step (the Gram-Schmidt coefficients stay on the device).
 #include <algorithm>
 #include <vector>
 

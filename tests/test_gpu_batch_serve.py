@@ -252,6 +252,48 @@ def test_moving_nodes_rebuilt_each_step(orbf):
     srv.close()
 
 
+def test_server_waits_for_device_written_coordinates(orbf):
+    """Coordinates produced on the device, on a side stream that is still
+    busy when the request is submitted: the request's slot stream waits for
+    the event Server.submit records on the submitting stream, so the build
+    sees the finished coordinates (a DM equal to a direct build of them)
+    and never the zeros the buffer held before."""
+    ctx = orbf.Context(0)
+    x0 = gpu(nodesets.ball(20000, 2)["x"])
+    n, m, l, delta = 50, 5, 3, 0.3
+    srv = orbf.Server(0, slots=2, arena=2 << 30, slot_scratch=512 << 20)
+    side = torch.cuda.Stream()
+    tickets, coords = [], []
+    for step in range(3):
+        x = torch.zeros_like(x0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            # a long product first, so the side stream is still busy at submit
+            a = torch.randn(4096, 4096, dtype=torch.float64, device="cuda:0")
+            for _ in range(4):
+                a = a @ a
+                a = a / a.abs().max()
+            th = 0.05 * (step + 1)
+            R = torch.tensor([[math.cos(th), -math.sin(th), 0.0],
+                              [math.sin(th), math.cos(th), 0.0],
+                              [0.0, 0.0, 1.0]], dtype=torch.float64,
+                             device="cuda:0")
+            x.copy_(x0 @ R.T + 0.0 * a[:1, :1])
+            tickets.append(srv.submit(x, n, m, l, delta))
+        coords.append(x)
+    _drain(srv, tickets)
+    torch.cuda.synchronize()
+    for t, x in zip(tickets, coords):
+        info = srv.result(t)
+        assert info["status"] == 0
+        got = srv.fetch(t)
+        ref = orbf.build_dm(x, n, m, l, delta, ctx=ctx)
+        same(got, ref)
+        srv.release(t)
+    srv.close()
+    _say("[gpu] server built device-written coordinates after their event")
+
+
 def test_server_budget_admission(orbf):
     """With an arena that holds about two requests at a time, requests wait
     for memory, the head is passed a bounded number of times, and every

@@ -627,3 +627,51 @@ def test_dm_laplacian_converges_on_gpu(orbf, ctx):
          f"observed order {slope:.2f} (estimate: {l - 1})")
     assert np.all(np.isfinite(errs))
     assert slope >= l - 1 - 0.25, (slope, errs)
+
+
+@pytest.mark.parametrize("case", ["ball20k_d03", "disk5k_d05_tau5"])
+def test_kept_sets_from_owner(orbf, ctx, case):
+    """The kept set of each center, R_k = {e : owner[e] = k}, rebuilt from
+    the GPU's owner array and checked against retention balls computed here
+    from the GPU's stencils and rho^2 (Sec. 4.1): the center keeps itself,
+    every kept node lies in the ball (d^2 <= (1-delta)^2 rho_k^2, a later
+    eligible stencil node), and with tau = inf the center keeps exactly the
+    ball nodes no earlier center kept."""
+    x, el, bnd, nrm, c = make(case)
+    tau = c.get("tau", math.inf)
+    got = orbf.build_dm(gpu(x), c["n"], c["m"], c["l"], c["delta"], tau=tau,
+                        eligible=None if el is None else gpu(el),
+                        boundary=None if bnd is None else gpu(bnd),
+                        normals=None if nrm is None else gpu(nrm), ctx=ctx)
+    knn = got["knn"].cpu().numpy().astype(np.int64)
+    rho2 = got["rho2"].cpu().numpy()
+    owner = got["owner"].cpu().numpy()
+    nc = int(got["n_centers"].item())
+    centers = got["centers"].cpu().numpy()[:nc]
+    N = len(x)
+    t = 1.0 - c["delta"]
+    t2 = t * t
+    xs = np.zeros((N, 3))
+    xs[:, :x.shape[1]] = x
+    diff = xs[knn] - xs[:, None, :]
+    d2 = (diff[..., 0] * diff[..., 0] + diff[..., 1] * diff[..., 1]) + \
+        diff[..., 2] * diff[..., 2]
+    elig = np.ones(N, bool) if el is None else el.astype(bool)
+    inball = (d2 <= t2 * rho2[:, None]) & (knn > np.arange(N)[:, None]) & \
+        elig[knn]
+    inball[:, 0] = False
+    assert np.array_equal(owner[centers], centers)
+    kept = owner[knn] == np.arange(N)[:, None]  # row k: kept positions
+    kept[:, 0] = False
+    cen = np.zeros(N, bool)
+    cen[centers] = True
+    # every kept node of a center is in its ball
+    assert not (kept[cen] & ~inball[cen]).any()
+    # every owned row appears in its owner's stencil
+    rows = np.nonzero((owner >= 0) & ~cen)[0]
+    assert (knn[owner[rows]] == rows[:, None]).any(1).all()
+    if math.isinf(tau):
+        earlier = owner[knn] < np.arange(N)[:, None]
+        assert np.array_equal(kept[cen], (inball & ~earlier)[cen])
+    _say(f"[gpu] kept sets {case}: {nc} centers, "
+         f"{int(kept[cen].sum()) + nc} kept rows checked")
