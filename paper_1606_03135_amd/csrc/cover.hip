@@ -152,8 +152,9 @@ __global__ __launch_bounds__(256) void ball_d2_quad_kernel(
 // Event-driven evaluation of the DAG.  cnt[j] starts as the number of
 // predecessors of j and counts those not yet decided as non-centers.  A
 // node is processed once, by the group of lanes that decided it:
-//   a center c claims every successor j: owner[j] = min(owner[j], c), and
-//     an undecided j becomes covered;
+//   a center c claims every successor j: owner[j] = min(owner[j], c); the
+//     claim that finds owner[j] still unset is the first, and j becomes
+//     covered (no separate state word, so one atomic per claim);
 //   a covered node decrements cnt of every successor; the lane that takes
 //     cnt[j] to 0 makes j a center (all of j's predecessors are then
 //     non-centers, so nothing else ever claims j).
@@ -219,7 +220,7 @@ template <bool MULTI>
 __device__ __forceinline__ void process_entry(
     int32_t entry, int32_t* stk, const CoverSet& one,
     const CoverSet* __restrict__ tab, const int32_t* __restrict__ setid,
-    const uint64_t* __restrict__ ball, int32_t* cnt, int32_t* state,
+    const uint64_t* __restrict__ ball, int32_t* cnt,
     int32_t* __restrict__ is_center, int32_t* __restrict__ qnext, int32_t* qn,
     int follow) {
   const int lane = (int)(threadIdx.x & 63), pl = lane & 15;
@@ -244,11 +245,10 @@ __device__ __forceinline__ void process_entry(
         const int32_t j = T.knn[(int64_t)c * n + q];
         const int32_t jg = (int32_t)(T.base + j);
         if (center) {
-          atomicMin(&T.owner[j], c);
-          if (atomicCAS(&state[jg], S_UNDECIDED, S_COVERED) == S_UNDECIDED)
-            dec[i] = jg;
+          // the first claim finds the owner still unset: j is covered now
+          // (a center j has no center predecessor, so is never claimed)
+          if (atomicMin(&T.owner[j], c) == INT32_MAX) dec[i] = jg;
         } else if (atomicSub(&cnt[jg], 1) == 1) {
-          __atomic_store_n(&state[jg], S_CENTER, __ATOMIC_RELAXED);
           T.owner[j] = j;
           is_center[jg] = 1;
           dec[i] = jg | kCenterBit;
@@ -295,9 +295,8 @@ template <bool MULTI>
 __global__ __launch_bounds__(256) void level_kernel(
     CoverSet one, const CoverSet* __restrict__ tab,
     const int32_t* __restrict__ setid, const uint64_t* __restrict__ ball,
-    int32_t* cnt, int32_t* state, int32_t* __restrict__ is_center,
-    int32_t* __restrict__ q0, int32_t* __restrict__ q1, int32_t* qc, int lv,
-    int follow) {
+    int32_t* cnt, int32_t* __restrict__ is_center, int32_t* __restrict__ q0,
+    int32_t* __restrict__ q1, int32_t* qc, int lv, int follow) {
   __shared__ int32_t stk[16 * kStack];
   const int32_t count = qc[lv % 3];
   if (blockIdx.x == 0 && threadIdx.x == 0) qc[(lv + 2) % 3] = 0;
@@ -308,7 +307,7 @@ __global__ __launch_bounds__(256) void level_kernel(
   for (int64_t t = (int64_t)blockIdx.x * 16 + grp; t < count;
        t += (int64_t)gridDim.x * 16)
     process_entry<MULTI>(cur[t], stk + grp * kStack, one, tab, setid, ball,
-                         cnt, state, is_center, nxt, qn, follow);
+                         cnt, is_center, nxt, qn, follow);
 }
 
 // One workgroup runs the remaining levels from `lv` until a queue is empty.
@@ -317,7 +316,7 @@ template <bool MULTI>
 __global__ __launch_bounds__(256) void finish_levels_kernel(
     CoverSet one, const CoverSet* __restrict__ tab,
     const int32_t* __restrict__ setid, const uint64_t* __restrict__ ball,
-    int64_t N, int32_t* cnt, int32_t* state, int32_t* __restrict__ is_center,
+    int64_t N, int32_t* cnt, int32_t* __restrict__ is_center,
     int32_t* __restrict__ q0, int32_t* __restrict__ q1, int32_t* qc, int lv) {
   __shared__ int32_t stk[16 * kStack];
   __shared__ int32_t count;
@@ -334,7 +333,7 @@ __global__ __launch_bounds__(256) void finish_levels_kernel(
     int32_t* nxt = (lv & 1) ? q0 : q1;
     for (int t = grp; t < count; t += 16)
       process_entry<MULTI>(cur[t], stk + grp * kStack, one, tab, setid, ball,
-                           cnt, state, is_center, nxt, &qc[(lv + 1) % 3],
+                           cnt, is_center, nxt, &qc[(lv + 1) % 3],
                            kFollowDeep);
     __threadfence();
   }
@@ -416,9 +415,9 @@ namespace {
 // the one it recorded).
 orbf_status run_levels(orbf_ctx* ctx, hipStream_t s, const CoverSet& one,
                        const CoverSet* tab, const int32_t* setid,
-                       uint64_t* ball, int32_t* cnt, int32_t* state,
-                       int32_t* flag, int32_t* q0, int32_t* q1, int32_t* qc,
-                       int64_t N, const void* key_ptr) {
+                       uint64_t* ball, int32_t* cnt, int32_t* flag,
+                       int32_t* q0, int32_t* q1, int32_t* qc, int64_t N,
+                       const void* key_ptr) {
   orbf_status st = ORBF_OK;
   const int64_t want_blocks = (N + 255) / 256;
   const unsigned gl =
@@ -429,12 +428,12 @@ orbf_status run_levels(orbf_ctx* ctx, hipStream_t s, const CoverSet& one,
       const int follow = lv < kWideLevels ? kFollowWide : kFollowDeep;
       if (tab)
         hipLaunchKernelGGL(level_kernel<true>, dim3(gl), dim3(256), 0, s, one,
-                           tab, setid, ball, cnt, state, flag, q0, q1, qc, lv,
+                           tab, setid, ball, cnt, flag, q0, q1, qc, lv,
                            follow);
       else
         hipLaunchKernelGGL(level_kernel<false>, dim3(gl), dim3(256), 0, s,
-                           one, tab, setid, ball, cnt, state, flag, q0, q1,
-                           qc, lv, follow);
+                           one, tab, setid, ball, cnt, flag, q0, q1, qc, lv,
+                           follow);
     }
   };
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -474,12 +473,10 @@ orbf_status run_levels(orbf_ctx* ctx, hipStream_t s, const CoverSet& one,
   }
   if (tab)
     hipLaunchKernelGGL(finish_levels_kernel<true>, dim3(1), dim3(256), 0, s,
-                       one, tab, setid, ball, N, cnt, state, flag, q0, q1, qc,
-                       lv);
+                       one, tab, setid, ball, N, cnt, flag, q0, q1, qc, lv);
   else
     hipLaunchKernelGGL(finish_levels_kernel<false>, dim3(1), dim3(256), 0, s,
-                       one, tab, setid, ball, N, cnt, state, flag, q0, q1, qc,
-                       lv);
+                       one, tab, setid, ball, N, cnt, flag, q0, q1, qc, lv);
   return hip_check(ctx, hipGetLastError(), "cover levels");
 }
 
@@ -529,8 +526,8 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   hipLaunchKernelGGL(seed_kernel, dim3(g), dim3(256), 0, s, cnt, N, state,
                      owner, flag, q0, qc, (int64_t)0);
   const CoverSet one{knn, owner, 0, n};
-  st = run_levels(ctx, s, one, nullptr, nullptr, ball, cnt, state, flag, q0,
-                  q1, qc, N, knn);
+  st = run_levels(ctx, s, one, nullptr, nullptr, ball, cnt, flag, q0, q1, qc,
+                  N, knn);
   if (st) return st;
   return finish_centers(ctx, flag, knn, ball, owner, N, n, centers, n_centers,
                         p);
@@ -560,8 +557,8 @@ orbf_status cover_multi_prologue(orbf_ctx* w, const double* xyz,
 orbf_status cover_multi_levels(orbf_ctx* ctx, const MultiCover& mc,
                                hipStream_t s) {
   const CoverSet none{nullptr, nullptr, 0, 0};
-  return run_levels(ctx, s, none, mc.tab, mc.setid, mc.ball, mc.cnt,
-                    mc.state, mc.flag, mc.q0, mc.q1, mc.qc, mc.total, mc.key);
+  return run_levels(ctx, s, none, mc.tab, mc.setid, mc.ball, mc.cnt, mc.flag,
+                    mc.q0, mc.q1, mc.qc, mc.total, mc.key);
 }
 
 void cover_multi_reset(const MultiCover& mc, hipStream_t s) {
