@@ -78,6 +78,10 @@ CASES = {
                              tau=2.0),
     # n + M > 72: the four-wavefront kernel
     "ball3k_l4_n105": dict(kind="ball", N=3000, n=105, m=5, l=4, delta=0.5),
+    # the largest stencil (n = 128: two mask words, two lanes per kNN row
+    # position) and the largest system the kernels serve (K = 143), with
+    # normal-derivative boundary rows of the same size
+    "disk3k_n128_l4": dict(kind="disk", N=3000, n=128, m=5, l=4, delta=0.5),
     "ball3k_l4_n90_d1": dict(kind="ball", N=3000, n=90, m=5, l=4, delta=1.0),
     "ball5k_l3_n60_d02": dict(kind="ball", N=5000, n=60, m=5, l=3,
                               delta=0.2),
@@ -286,6 +290,38 @@ def test_edge_cases(orbf, ctx):
     ctx.sync()
     assert np.array_equal(k.cpu().numpy()[:, 0], np.arange(100))
     assert (r.cpu().numpy() == 0).all()
+
+
+def test_degenerate_inputs(orbf, ctx):
+    """Degenerate inputs the method admits, against the oracle:
+    - no eligible node: no centers, every owner -1, the weights pass does
+      nothing and the CSR has only empty rows;
+    - no eligible node but boundary rows: the CSR holds just those rows;
+    - N = 0 is an error (EINVAL), and an empty batch is a no-op."""
+    D = nodesets.disk(500, 60, 1)
+    x = D["x"]
+    none = np.zeros(len(x), np.uint8)
+    _say("[gpu] degenerate: no eligible node")
+    for with_bnd in (False, True):
+        kw = dict(eligible=none)
+        if with_bnd:
+            kw.update(boundary=D["boundary"], normals=D["normals"])
+        ref = oracle.build_dm(x, 31, 5, 4, 0.5, **kw)
+        got = orbf.build_dm(gpu(x), 31, 5, 4, 0.5,
+                            **{k: gpu(v) for k, v in kw.items()}, ctx=ctx)
+        assert int(got["n_centers"].item()) == 0
+        assert np.array_equal(got["owner"].cpu().numpy(), ref["owner"])
+        assert np.array_equal(got["row_ptr"].cpu().numpy(), ref["row_ptr"])
+        assert np.array_equal(got["col"].cpu().numpy(), ref["col"])
+        rows = ref["owner"] >= 0
+        if rows.any():
+            assert row_err(got["W"].cpu().numpy()[rows], ref["W"][rows]) <= TOL
+    with pytest.raises(orbf.OrbfError) as e:
+        orbf.build_nodes_knn(ctx, gpu(np.zeros((0, 2))), 1)
+    assert e.value.code == orbf.EINVAL
+    L = orbf.lib()
+    assert L.orbf_build_dm_batched(ctx._h, None, 0) == 0
+    ctx.sync()
 
 
 def test_errors(orbf, ctx):
