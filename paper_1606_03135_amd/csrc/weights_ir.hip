@@ -49,20 +49,25 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
   __shared__ double xs[S * NB];  // X by unknown index (also assembly strip)
   __shared__ float rs[S * NB];   // residual by matrix row
 
-  const int lane = threadIdx.x;
-  const int r = lane & 7, c = lane >> 3;
+  const int lane0 = threadIdx.x;
   const int n = P.n, K = P.K, d = P.d, M = P.M, m = P.m, op = P.op;
   double* psi_s = dyn_s;
   double* lpsi_s = dyn_s + n * M;
   double* pw_s = lpsi_s + NB * M;
   double* strip = xs;
-  for (int t = lane; t < 3 * M; t += 64) ex_s[t] = P.ex[t];
+  for (int t = lane0; t < 3 * M; t += 64) ex_s[t] = P.ex[t];
   // eliminations write only values in [0, K) here, so with this start no
   // rank read below can index out of range
-  for (int t = lane; t < S; t += 64) srank[t] = 0;
+  for (int t = lane0; t < S; t += 64) srank[t] = 0;
 
   const int64_t total = *P.n_centers;
   for (int64_t ci = blockIdx.x; ci < total; ci += gridDim.x) {
+    // the lane's coordinates, opaque to the compiler in every iteration:
+    // values derived from them are recomputed per stencil instead of being
+    // hoisted out of the stencil loop and held (spilled) across it
+    int lane = lane0;
+    __asm__ volatile("" : "+v"(lane));
+    const int r = lane & 7, c = lane >> 3;
     const int32_t ck = P.centers[ci];
     if ((uint32_t)ck >= (uint64_t)P.N) {
       if (lane == 0) report(P.st, ORBF_EINVAL, ck);
