@@ -360,6 +360,28 @@ def bench_ball(args, torch, orbf, nodesets):
             "corrections_max": int(st.max()),
             "fp64_fallback_rows": float((~ok).mean())}
         del W64, r32
+    # what this device reaches on the two units the roofline is priced
+    # against, next to the published peaks: the FP64 FMA rate of
+    # independent dependency chains on every SIMD, and a plain elementwise
+    # copy of COPY_BYTES (read + write), both timed after the builds
+    fma = ctx.measure_fp64_fma()
+    a = torch.full((COPY_BYTES // 8,), 1.0, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    e0.record()
+    for _ in range(5):
+        torch.neg(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    cms = e0.elapsed_time(e1) / 5
+    out["measured_peaks"] = {
+        "fp64_fma_tflops": fma,
+        "fp64_fma_frac_of_published": fma / FP64_PEAK_TFLOPS,
+        "copy_gbs": 2 * COPY_BYTES / (cms * 1e-3) / 1e9,
+        "copy_frac_of_published": 2 * COPY_BYTES / (cms * 1e-3) / 1e9
+        / HBM_PEAK_GBS,
+        "roofline_frac_vs_measured_fma": achieved / fma}
+    del a, b
     if args.copy_calibration:
         # plain elementwise copy: reads and writes COPY_BYTES each
         a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev)

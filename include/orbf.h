@@ -448,6 +448,14 @@ orbf_status orbf_get_schedules(orbf_ctx* ctx, int32_t* out, int cap,
  * last launch.  Valid after orbf_sync. */
 orbf_status orbf_phase_times(orbf_ctx* ctx, double* ms5 /* host, 5 */);
 
+/* Measurement helper, not a step of the method: the FP64 vector FMA rate
+ * this device reaches (TFLOP/s, written to *tflops, host), from a kernel of
+ * independent FMA chains at two wavefronts per SIMD, best of three timed
+ * launches after one warm-up.  Blocking (synchronises the context's
+ * stream); uses the context's scratch.  It is reported beside the published
+ * FP64 peak that roofline fractions are taken against. */
+orbf_status orbf_measure_fp64_fma(orbf_ctx* ctx, double* tflops);
+
 /* ------------------------------------------------------------------------
  * Batched builds: many independent node sets in one call.
  * ---------------------------------------------------------------------- */

@@ -136,6 +136,8 @@ def lib():
         L.orbf_bdf_rhs.restype = _I
         L.orbf_phase_times.argtypes = [_P, ctypes.POINTER(_D)]
         L.orbf_phase_times.restype = _I
+        L.orbf_measure_fp64_fma.argtypes = [_P, ctypes.POINTER(_D)]
+        L.orbf_measure_fp64_fma.restype = _I
         L.orbf_build_dm_batched.argtypes = [_P, ctypes.POINTER(SetDesc), _I]
         L.orbf_build_dm_batched.restype = _I
         L.orbf_set_workers.argtypes = [_P, _I]
@@ -223,6 +225,13 @@ class Context:
         a = (_D * 5)()
         self.check(lib().orbf_phase_times(self._h, a))
         return list(a)
+
+    def measure_fp64_fma(self):
+        """The FP64 vector FMA rate this device reaches, in TFLOP/s (a
+        measurement helper, blocking)."""
+        v = _D()
+        self.check(lib().orbf_measure_fp64_fma(self._h, ctypes.byref(v)))
+        return v.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "liborbf.so")
 SOURCES = ["api.hip", "scan.hip", "knn.hip", "cover.hip", "weights.hip",
            "weights_reg.hip", "weights_ir.hip", "weights_wg.hip",
            "lebesgue.hip", "csr.hip", "gershgorin.hip", "krylov.hip", "ilu.hip",
-           "batch.hip"]
+           "batch.hip", "peak.hip"]
 ARCH = os.environ.get("ORBF_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,

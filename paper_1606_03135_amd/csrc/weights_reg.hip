@@ -44,7 +44,10 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
   __shared__ int cols_s[S];
   __shared__ int8_t ex_s[3 * 36];
   __shared__ double ubuf[8 * LC];  // [c][jj] pivot row
-  __shared__ double lbuf[8 * L];   // [r][ii] multipliers
+  // [ii][r] multipliers: the column's 64-bit registers are stored as they
+  // are (the [r][ii] layout made the compiler copy them into consecutive
+  // pairs first, 16 moves per step)
+  __shared__ double lbuf[8 * L];
   __shared__ double dinv[S];
   __shared__ double strip[LC * 64];  // assembly staging, one row per lane
   __shared__ int srank[S];         // elimination step of each row slot
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
           if (c == cc) {
             sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
               constexpr int ii = decltype(iic)::value;
-              lbuf[r * L + ii] = a[ii][kb];
+              lbuf[ii * 8 + r] = a[ii][kb];
             });
           }
           double upiv = 0.0;
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
                   constexpr int jj = decltype(jjc)::value;
                   ubuf[c * LC + jj] = a[ii][jj];
                 });
-                if (c == cc) lbuf[r * L + ii] = 0.0;
+                if (c == cc) lbuf[ii * 8 + r] = 0.0;
               }
             }
           });
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
           });
           sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
             constexpr int ii = decltype(iic)::value;
-            lv[ii] = lbuf[r * L + ii];
+            lv[ii] = lbuf[ii * 8 + r];
           });
           // Gauss-Jordan: every row but the pivot row is eliminated, the
           // rows pivoted earlier included, so no back substitution follows
