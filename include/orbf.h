@@ -416,12 +416,15 @@ typedef enum orbf_schedule {
                              (K <= 72): fewer registers                      */
   ORBF_SCHED_GROUP16 = 2, /* four wavefronts on a 16 x 16 lane grid, 16
                              right-hand sides per pass (K <= 144)            */
-  ORBF_SCHED_SPLIT = 3    /* one wavefront per stencil, with 8, 16 or 24
+  ORBF_SCHED_SPLIT = 3,   /* one wavefront per stencil, with 8, 16 or 24
                              right-hand sides per pass chosen per stencil
                              from its retained-row count p (p <= 8, <= 16,
                              above): stencils are sorted into three lists on
                              the device and each list is one launch
                              (K <= 72)                                       */
+  ORBF_SCHED_MATRIX = 4   /* one wavefront per stencil, blocked elimination
+                             whose updates run on the FP64 matrix cores,
+                             16 right-hand sides per pass (32 < K <= 80)     */
 } orbf_schedule;
 
 /* Set (or with ORBF_SCHED_DEFAULT clear) the schedule of (K, pclass).

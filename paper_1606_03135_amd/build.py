@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liborbf.so")
 SOURCES = ["api.hip", "scan.hip", "knn.hip", "cover.hip", "weights.hip",
-           "weights_reg.hip", "weights_ir.hip", "weights_wg.hip",
+           "weights_reg.hip", "weights_ir.hip", "weights_wg.hip", "weights_mfma.hip",
            "lebesgue.hip", "csr.hip", "gershgorin.hip", "krylov.hip", "ilu.hip",
            "batch.hip", "peak.hip"]
 ARCH = os.environ.get("ORBF_OFFLOAD_ARCH", "gfx950")

@@ -495,7 +495,9 @@ orbf_status orbf_set_schedule(orbf_ctx* ctx, int K, int pclass,
     return fail(ctx, ORBF_EINVAL, "one-wavefront schedules need K <= 72");
   if (schedule == ORBF_SCHED_GROUP16 && K > 144)
     return fail(ctx, ORBF_EINVAL, "the workgroup schedule needs K <= 144");
-  if (schedule < ORBF_SCHED_DEFAULT || schedule > ORBF_SCHED_SPLIT)
+  if (schedule == ORBF_SCHED_MATRIX && (K <= 32 || K > 80))
+    return fail(ctx, ORBF_EINVAL, "the matrix-core schedule needs 32 < K <= 80");
+  if (schedule < ORBF_SCHED_DEFAULT || schedule > ORBF_SCHED_MATRIX)
     return fail(ctx, ORBF_EINVAL, "unknown schedule");
   auto& t = ctx->schedules;
   for (size_t i = 0; i + 2 < t.size(); i += 3)

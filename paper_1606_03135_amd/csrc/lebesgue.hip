@@ -28,10 +28,12 @@
 // latencies on the critical path.  So after a few levels every node still
 // undecided that has a ball is solved at once (its keep bits depend on its
 // own stencil only, whatever it turns out to be), and the rest of the DAG
-// settles by integer propagation alone, one launch per level.  (One
-// workgroup running all the remaining levels in a single launch measured
-// slower: 10.7 against 4.9 ms on the 100k disk in generation order, since
-// every level's chain of dependent atomics then funnels through one CU.)
+// settles by integer propagation alone, one launch per level, one group of
+// sixteen lanes per decided node (a covered node's count-offs spread over
+// its group rather than looped by one lane).  (One workgroup running all
+// the remaining levels in a single launch measured slower: 10.7 against
+// 4.9 ms on the 100k disk in generation order, since every level's chain
+// of dependent atomics then funnels through one CU.)
 #include "orbf_internal.hpp"
 #include "weights_common.hpp"
 
@@ -42,6 +44,12 @@ namespace {
 constexpr int64_t kSolveGrid = 4096;  // accept-mode solve blocks per level
 constexpr unsigned kPropBlocks = 256;   // propagation: 4 wavefronts a block
 constexpr int64_t kSolvedLevels = 4;    // levels solved one by one
+constexpr unsigned kFollowBlocks = 512; // propagation-only levels: 16 groups
+// decisions a group follows itself per entry in the propagation-only
+// levels (100k disk in generation order, whole build: 4.75-4.96 ms at 1,
+// 5.38 at 0, 5.30 at 2, 5.43 at 4, 5.80 at 16, 6.53 at 64: long follows
+// serialise what the level spreads over the device)
+constexpr int kFollow = 1;
 
 // A covered node keeps L_UNDECIDED: its owner word (set by the first
 // keeping center) is what marks it.
@@ -152,6 +160,114 @@ __global__ __launch_bounds__(256) void lprop_kernel(
   }
 }
 
+// After the speculative solve every node that can still become a center has
+// its keep bits, so the rest of the DAG is integer propagation in any order.
+// One group of sixteen lanes per entry (lane p takes stencil positions
+// p + 16 i): an entry is a center (j >= 0: its rejected ball nodes count it
+// off, its kept ones get its offer) or a node just covered (j | INT32_MIN:
+// its ball nodes count it off).  The decisions a group makes are followed
+// by the group itself through a small LDS stack, up to `follow` of them per
+// entry; the rest go to the next level's list.  Every node is decided once,
+// so it enters a list at most once.
+constexpr int kLStack = 32;
+
+__device__ __forceinline__ void lfollow_entry(
+    int32_t entry, int32_t* stk, const int32_t* __restrict__ knn, int n,
+    const uint64_t* __restrict__ ball, const uint64_t* __restrict__ acc,
+    int32_t* open, int32_t* state, int32_t* owner, int32_t* next,
+    int64_t* next_count, int follow) {
+  const int lane = (int)(threadIdx.x & 63), pl = lane & 15;
+  const int gshift = lane & 48;  // first lane of the group in the wave
+  const uint32_t below = (1u << pl) - 1u;
+  constexpr int32_t kNone = INT32_MAX;  // no decision (N < 2^25)
+  int sp = 0;
+  int32_t e = entry;
+  for (;;) {
+    const bool covered = e < 0;
+    const int32_t c = e & INT32_MAX;
+    const uint64_t b0 = ball[2 * (int64_t)c], b1 = ball[2 * (int64_t)c + 1];
+    const uint64_t k0 = covered ? 0ull : acc[2 * (int64_t)c];
+    const uint64_t k1 = covered ? 0ull : acc[2 * (int64_t)c + 1];
+    int32_t dec[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = pl + 16 * i;
+      dec[i] = kNone;
+      const uint64_t bits = q < 64 ? b0 : b1;
+      const uint64_t keep = q < 64 ? k0 : k1;
+      if (q < n && ((bits >> (q & 63)) & 1ull)) {
+        const int32_t j = knn[(int64_t)c * n + q];
+        if (covered || !((keep >> (q & 63)) & 1ull)) {
+          const int32_t left = __hip_atomic_fetch_add(
+              &open[j], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (left == 1) {
+            __hip_atomic_store(&state[j], L_CENTER, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            dec[i] = j;
+          }
+        } else if (__hip_atomic_fetch_min(&owner[j], c, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) ==
+                   INT32_MAX) {
+          dec[i] = j | INT32_MIN;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (16 * i >= n) break;
+      const uint32_t m =
+          (uint32_t)(__ballot(dec[i] != kNone) >> gshift) & 0xFFFFu;
+      if (m == 0u) continue;
+      const int k = __popc(m);
+      int room = kLStack - sp;
+      if (room > follow) room = follow;
+      const int kept = k < room ? k : room;
+      const int r = __popc(m & below);
+      int64_t base = 0;
+      if (k > kept) {
+        if (pl == __ffs(m) - 1)
+          base = __hip_atomic_fetch_add(next_count, (int64_t)(k - kept),
+                                        __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        base = __shfl(base, gshift + __ffs(m) - 1, 64);
+      }
+      if (dec[i] != kNone) {
+        if (r < kept)
+          stk[sp + r] = dec[i];
+        else
+          __hip_atomic_store(&next[base + r - kept], dec[i], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      sp += kept;
+      follow -= kept;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (sp == 0) break;
+    e = stk[--sp];
+  }
+}
+
+// One propagation-only level: the entries of `list` (count *count), one
+// group of sixteen lanes each; *zero (the count the previous level read) is
+// cleared for the next.
+__global__ __launch_bounds__(256) void lfollow_kernel(
+    const int32_t* __restrict__ list, const int64_t* __restrict__ count,
+    const int32_t* __restrict__ knn, int n, const uint64_t* __restrict__ ball,
+    const uint64_t* __restrict__ acc, int32_t* open, int32_t* state,
+    int32_t* owner, int32_t* next, int64_t* next_count, int64_t* zero,
+    int follow) {
+  __shared__ int32_t stk[16 * kLStack];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *zero = 0;
+  const int grp = threadIdx.x >> 4;
+  const int64_t cnt = *count;
+  for (int64_t t = (int64_t)blockIdx.x * 16 + grp; t < cnt;
+       t += (int64_t)gridDim.x * 16)
+    lfollow_entry(list[t], stk + grp * kLStack, knn, n, ball, acc, open,
+                  state, owner, next, next_count, follow);
+}
+
 // centers own themselves; flags for the ascending center list
 __global__ __launch_bounds__(256) void lfinal_kernel(
     const int32_t* __restrict__ state, int64_t N, int32_t* __restrict__ owner,
@@ -241,6 +357,9 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
   const unsigned gs = (unsigned)(N < kSolveGrid ? N : kSolveGrid);
   const unsigned gp = (unsigned)((N + 3) / 4 < kPropBlocks ? (N + 3) / 4
                                                             : kPropBlocks);
+  const unsigned gf = (unsigned)((N + 15) / 16 < kFollowBlocks
+                                     ? (N + 15) / 16
+                                     : kFollowBlocks);
   int64_t level = 0;
   bool solving = true;
   auto solve = [&](int32_t* l, int64_t* c) -> orbf_status {
@@ -258,10 +377,16 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
   for (;;) {
     for (int r = 0; r < batch; ++r, ++level) {
       const int a = (int)(level % 3), b = (a + 1) % 3, z = (a + 2) % 3;
-      if (solving && (st = solve(list[a], cnt + a))) return st;
-      hipLaunchKernelGGL(lprop_kernel, dim3(gp), dim3(256), 0, s, list[a],
-                         cnt + a, P0.knn, n, ball, acc, open, state, owner,
-                         list[b], cnt + b, cnt + z);
+      if (solving) {
+        if ((st = solve(list[a], cnt + a))) return st;
+        hipLaunchKernelGGL(lprop_kernel, dim3(gp), dim3(256), 0, s, list[a],
+                           cnt + a, P0.knn, n, ball, acc, open, state, owner,
+                           list[b], cnt + b, cnt + z);
+      } else {
+        hipLaunchKernelGGL(lfollow_kernel, dim3(gf), dim3(256), 0, s, list[a],
+                           cnt + a, P0.knn, n, ball, acc, open, state, owner,
+                           list[b], cnt + b, cnt + z, kFollow);
+      }
     }
     int64_t next = 0;
     hipError_t e = hipMemcpyAsync(&next, cnt + (int)(level % 3), sizeof next,

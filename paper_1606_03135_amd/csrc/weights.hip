@@ -259,6 +259,8 @@ orbf_status launch_weights(orbf_ctx* ctx, orbf_op op, int m, int l, int n,
   const bool split_default = sched == ORBF_SCHED_DEFAULT && a->N >= 65536;
   // false only if no kernel serves K (the entry point admits K <= 144)
   auto fp64 = [&](const WeightsParams& Q) -> bool {
+    if (sched == ORBF_SCHED_MATRIX && launch_weights_mfma(ctx, Q, grid))
+      return true;
     if ((sched == ORBF_SCHED_SPLIT || split_default) && split(Q)) return true;
     if (sched == ORBF_SCHED_GROUP16 && launch_weights_wg(ctx, Q, work))
       return true;

@@ -188,6 +188,7 @@ bool launch_weights_reg(orbf_ctx* ctx, const WeightsParams& P, int64_t grid,
                         int pl = 2);
 bool launch_weights_ir(orbf_ctx* ctx, const WeightsParams& P, int64_t grid);
 bool launch_weights_wg(orbf_ctx* ctx, const WeightsParams& P, int64_t work);
+bool launch_weights_mfma(orbf_ctx* ctx, const WeightsParams& P, int64_t grid);
 void launch_ir_prepare(orbf_ctx* ctx, int32_t* ir_steps, int64_t N,
                        int64_t* fb_count);
 orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,

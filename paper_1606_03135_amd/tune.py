@@ -16,7 +16,8 @@ import time
 
 import paper_1606_03135_amd as orbf
 
-SCHEDULES = {"wave16": 0, "wave8": 1, "group16": 2, "split": 3}
+SCHEDULES = {"wave16": 0, "wave8": 1, "group16": 2, "split": 3,
+             "matrix": 4}
 NAMES = {v: k for k, v in SCHEDULES.items()}
 
 

@@ -365,7 +365,7 @@ def test_schedules_and_tuner(orbf):
     ref = oracle.build_dm(x, n, m, l, delta)
     own = ref["owner"] >= 0
     out = {}
-    for name in ("wave16", "wave8", "group16", "split"):
+    for name in ("wave16", "wave8", "group16", "matrix", "split"):
         tune.set_schedule(ctx, K, pc, name)
         r = orbf.build_dm(xd, n, m, l, delta, ctx=ctx)
         W = r["W"].cpu().numpy()
@@ -389,6 +389,53 @@ def test_schedules_and_tuner(orbf):
     _say(f"[gpu] tuner: {len(rep)} classes in {secs:.1f} s")
     assert {(r["K"], r["pclass"]) for r in rep} == {
         (K_, p_) for K_, p_, _ in tune.get_schedules(ctx)}
+
+
+@pytest.mark.parametrize("case", ["disk_K46", "ball_K60", "disk_K67_rows"])
+def test_matrix_schedule_matches_oracle(orbf, case):
+    """The matrix-core schedule (blocked elimination with FP64 matrix
+    instructions) against the oracle at each tile count it instantiates
+    (3, 4 and 5 row tiles of 16: K = 46, 60, 67), on covered rows and on
+    explicit Neumann rows with normals; several right-hand-side passes
+    where a stencil keeps more than 16 rows."""
+    from paper_1606_03135_amd import tune
+    ctx = orbf.Context(0)
+    if case == "disk_K46":
+        D = nodesets.disk(5000, 200, 3)
+        x, n, m, l, delta = D["x"], 31, 5, 4, 0.2
+    elif case == "ball_K60":
+        x, n, m, l, delta = nodesets.ball(6000, 3)["x"], 40, 5, 3, 0.2
+    else:
+        D = nodesets.disk(4000, 160, 4, refine=True)
+        x, n, m, l, delta = D["x"], 46, 5, 5, 0.5
+    d = x.shape[1]
+    M = math.comb(l + d, d)
+    K = n + M
+    pc = tune.pclass(n, d, delta)
+    tune.set_schedule(ctx, K, pc, "matrix")
+    tune.set_schedule(ctx, K, 0, "matrix")
+    tune.set_schedule(ctx, K, 1, "matrix")
+    if case == "disk_K67_rows":
+        bd = D["boundary"]
+        ref = oracle.build_dm(x, n, m, l, delta, eligible=D["eligible"],
+                              boundary=bd, normals=D["normals"])
+        r = orbf.build_dm(gpu(x), n, m, l, delta, eligible=gpu(D["eligible"]),
+                          boundary=gpu(bd), normals=gpu(D["normals"]),
+                          ctx=ctx)
+    else:
+        ref = oracle.build_dm(x, n, m, l, delta)
+        r = orbf.build_dm(gpu(x), n, m, l, delta, ctx=ctx)
+    assert np.array_equal(r["owner"].cpu().numpy(), ref["owner"])
+    W = r["W"].cpu().numpy()
+    own = ref["owner"] >= 0
+    err = float((np.abs(W[own] - ref["W"][own]).max(1) /
+                 np.abs(ref["W"][own]).max(1)).max())
+    pmax = int(np.bincount(ref["owner"][own]).max())
+    _say(f"[gpu] matrix schedule {case}: K={K}, up to {pmax} rows per "
+         f"stencil, max row rel err {err:.2e}")
+    assert err <= 1e-9
+    with pytest.raises(orbf.OrbfError):
+        tune.set_schedule(ctx, 81, 0, "matrix")  # beyond five row tiles
 
 
 def test_split_schedule_without_cached_counts(orbf):
