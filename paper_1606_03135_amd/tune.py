@@ -2,8 +2,9 @@
 
 Stencils of one system size K = n + M can be solved by a one-wavefront
 kernel with 16 or 8 right-hand sides per pass, or with 8, 16 or 24 chosen
-per stencil from its retained rows ("split"; K <= 72), or by a four-
-wavefront workgroup kernel (K <= 144).  Which is fastest depends on K and on
+per stencil from its retained rows ("split"; K <= 72), by a four-
+wavefront workgroup kernel (K <= 144), or by the one-wavefront blocked
+elimination on the FP64 matrix cores ("matrix"; 32 < K <= 80).  Which is fastest depends on K and on
 how many rows a stencil keeps (p-class: n (1 - delta)^d above 8 or not).
 The tuner times each candidate on the largest node set of each (K, p-class)
 present in a workload, with HIP events around the weights kernel, and keeps
@@ -22,11 +23,14 @@ NAMES = {v: k for k, v in SCHEDULES.items()}
 
 
 def _candidates(K):
+    out = []
     if K <= 72:
-        return ["split", "wave16", "wave8", "group16"]
-    if K <= 144:
-        return ["group16"]
-    return []
+        out = ["split", "wave16", "wave8", "group16"]
+    elif K <= 144:
+        out = ["group16"]
+    if 32 < K <= 80:
+        out.append("matrix")
+    return out
 
 
 def pclass(n, d, delta):
