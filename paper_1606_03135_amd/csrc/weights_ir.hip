@@ -121,6 +121,8 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
     wsync();
 
     // ---- assemble A_hat (FP64 entries, stored as FP32) ----
+    // A_hat is symmetric: only its blocks jj >= ii are computed, the others
+    // are taken from their mirror blocks below
     float a[L][L];
     sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
       constexpr int ii = decltype(iic)::value;
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
       const double xi1 = ri ? xi_s[3 * i + 1] : 0.0;
       const double xi2 = ri ? xi_s[3 * i + 2] : 0.0;
 #pragma clang loop unroll(disable)
-      for (int jj = 0; jj < L; ++jj) {
+      for (int jj = ii; jj < L; ++jj) {
         const int j = 8 * jj + c;
         double v = 0.0;
         if (i < n && j < n) {
@@ -144,11 +146,24 @@ __global__ __launch_bounds__(64, 2) void weights_ir_kernel(WeightsParams P) {
         }
         strip[jj * 64 + lane] = v;
       }
-      sfor<0, L>([&](auto jjc) __attribute__((always_inline)) {
+      sfor<ii, L>([&](auto jjc) __attribute__((always_inline)) {
         constexpr int jj = decltype(jjc)::value;
         a[ii][jj] = (float)strip[jj * 64 + lane];
       });
     });
+    // entry (8 ii + r, 8 jj + c) equals entry (8 jj + c, 8 ii + r), which
+    // lane (c, r) holds in block (jj, ii)
+    {
+      const int tr = (c + 8 * r) << 2;
+      sfor<1, L>([&](auto iic) __attribute__((always_inline)) {
+        constexpr int ii = decltype(iic)::value;
+        sfor<0, ii>([&](auto jjc) __attribute__((always_inline)) {
+          constexpr int jj = decltype(jjc)::value;
+          a[ii][jj] = __int_as_float(
+              __builtin_amdgcn_ds_bpermute(tr, __float_as_int(a[jj][ii])));
+        });
+      });
+    }
 
     // ---- FP32 Gauss-Jordan, multipliers kept in place ----
     uint32_t act[L];

@@ -232,7 +232,9 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
       // ---- assemble [A_hat | B_hat] ----
       // Entries of local row ii are computed by a compact runtime loop into
       // this lane's LDS strip and read back into registers: no per-entry
-      // code duplication, and each lane reads only its own writes.
+      // code duplication, and each lane reads only its own writes.  A_hat
+      // is symmetric, so only its blocks jj >= ii are computed; the others
+      // are taken from their mirror blocks below.
       double a[L][LC];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
         constexpr int ii = decltype(iic)::value;
@@ -242,7 +244,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         const double xi1 = ri ? xi_s[3 * i + 1] : 0.0;
         const double xi2 = ri ? xi_s[3 * i + 2] : 0.0;
 #pragma clang loop unroll(disable)
-        for (int jj = 0; jj < LC; ++jj) {
+        for (int jj = ii; jj < LC; ++jj) {
           double v = 0.0;
           if (jj < L) {
             const int j = 8 * jj + c;
@@ -271,11 +273,24 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
           }
           strip[jj * 64 + lane] = v;
         }
-        sfor<0, LC>([&](auto jjc) __attribute__((always_inline)) {
+        sfor<ii, LC>([&](auto jjc) __attribute__((always_inline)) {
           constexpr int jj = decltype(jjc)::value;
           a[ii][jj] = strip[jj * 64 + lane];
         });
       });
+      // the blocks below the diagonal: entry (8 ii + r, 8 jj + c) equals
+      // entry (8 jj + c, 8 ii + r), which lane (c, r) holds in block (jj, ii)
+      // (the same bits: the mirrored differences only change sign)
+      {
+        const int tr = (c + 8 * r) << 2;
+        sfor<1, L>([&](auto iic) __attribute__((always_inline)) {
+          constexpr int ii = decltype(iic)::value;
+          sfor<0, ii>([&](auto jjc) __attribute__((always_inline)) {
+            constexpr int jj = decltype(jjc)::value;
+            a[ii][jj] = bperm_f64(tr, a[jj][ii]);
+          });
+        });
+      }
       // ---- LU with row partial pivoting, rows kept in place ----
       // act[ii]: magnitude mask of local row ii (0 once the row has been
       // used as a pivot).  Pivoted rows keep their U entries and receive

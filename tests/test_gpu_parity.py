@@ -504,6 +504,23 @@ def test_singular_stencils(orbf, n, l, prec):
     assert np.isnan(W).all()
 
 
+def test_singular_stencils_matrix_schedule(orbf):
+    """The same exactly singular line under the matrix-core schedule
+    (K = 40 + 6 = 46, three row tiles): ESINGULAR at sync and NaN rows."""
+    from paper_1606_03135_amd import tune
+    ctx = orbf.Context(0)
+    N, n, l = 200, 40, 2
+    x = np.zeros((N, 2))
+    x[:, 0] = (np.arange(N) + 0.5) / N
+    for pc in (0, 1):
+        tune.set_schedule(ctx, n + 6, pc, "matrix")
+    r = orbf.build_dm(gpu(x), n, 3, l, 1.0, ctx=ctx, sync=False)
+    with pytest.raises(orbf.OrbfError) as e:
+        ctx.sync()
+    assert e.value.code == orbf.ESINGULAR
+    assert np.isnan(r["W"].cpu().numpy()).all()
+
+
 OP_CASES = {
     # name: (node set, n, m, l, delta, operator, precision)
     "ball20k_dx": ("ball", 20000, 50, 5, 3, 0.3, "DX", "fp64"),
