@@ -47,7 +47,7 @@ __device__ __forceinline__ double readlane_f64_knn(double v, int lane) {
 
 // (d, j) < (e, k) in the stencil order: squared distance, then index
 __device__ __forceinline__ bool key_less(double d, int j, double e, int k) {
-  return d < e || (d == e && j < k);
+  return (d < e) | ((d == e) & (j < k));  // bitwise: no branches
 }
 
 // Value of lane ^ STRIDE.  Strides 1 and 2 are quad permutations and 8 is a
@@ -85,8 +85,14 @@ __device__ __forceinline__ void bitonic_stage(double (&d)[NR], int (&j)[NR],
     const double pd = xor_lane_f64<STRIDE>(d[h]);
     const int pj = xor_lane<STRIDE>(j[h]);
     const bool keep_min = ((i & STRIDE) == 0) == ((i & SIZE) == 0);
-    const bool take = keep_min ? key_less(pd, pj, d[h], j[h])
-                               : key_less(d[h], j[h], pd, pj);
+    // keys are distinct except the identical padding keys, so "the
+    // partner's key is the smaller" decides both directions; bitwise
+    // operators keep it free of branches (a short-circuit form with one
+    // comparison per direction compiled to about 30 exec-mask scalar
+    // instructions and several branches per stage: 1M-node ball kNN
+    // 2.86 -> 2.31 ms, the same stencils)
+    const bool lt = (pd < d[h]) | ((pd == d[h]) & (pj < j[h]));
+    const bool take = keep_min == lt;
     d[h] = take ? pd : d[h];
     j[h] = take ? pj : j[h];
   }
@@ -415,8 +421,13 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
           for (int64_t t = s0 + hl; __ballot(t < s1) != 0ull; t += 32) {
             bool keep = false;
             double d2 = 0.0;
+            int32_t pj = 0;
             if (t < s1) {
               const double* p = xs + t * d;
+              // the node index is loaded with the coordinates, so one wait
+              // covers both (loaded only for kept candidates it was a
+              // second dependent round trip per step)
+              pj = perm[t];
               d2 = exact_sqdist(q0, q1, q2, p[0], p[1], d == 3 ? p[2] : 0.0, d);
               if (d2 == 0.0 && t != qs) dup = true;
               keep = d2 < T;
@@ -426,7 +437,7 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
               const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
               if (pos < kKeep) {
                 kd[w][pos] = d2;
-                kj[w][pos] = perm[t];
+                kj[w][pos] = pj;
               }
             }
             base += __popcll(m);
