@@ -317,15 +317,18 @@ __global__ __launch_bounds__(256) void cell_count_kernel(
   }
 }
 
+// Also turns cell_of into the inverse permutation: cell_of[i] = position
+// of node i in cell order (each thread reads and then overwrites its own).
 __global__ __launch_bounds__(256) void cell_scatter_kernel(
     const double* __restrict__ x, int64_t N, int d,
-    const int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank,
+    int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank,
     const int64_t* __restrict__ start, int32_t* __restrict__ perm,
     double* __restrict__ xs) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * 256) {
     int64_t pos = start[cell_of[i]] + rank[i];
     perm[pos] = (int32_t)i;
+    cell_of[i] = (int32_t)pos;
     for (int a = 0; a < d; ++a) xs[pos * d + a] = x[i * d + a];
   }
 }
@@ -547,7 +550,7 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   hipLaunchKernelGGL(knn_query_kernel, dim3((unsigned)qblocks),
                      dim3(64 * kWaves), 0, s, xs, perm, cstart, gp, N, d, n,
                      knn, rho2, d2, ctx->status);
-  ctx->d2_cache = {xyz, knn, N, d, n, d2, perm};
+  ctx->d2_cache = {xyz, knn, N, d, n, d2, perm, cell_of};
   return hip_check(ctx, hipGetLastError(), "knn");
 }
 

@@ -67,6 +67,7 @@ struct D2Cache {
   int d = 0, n = 0;
   const double* d2 = nullptr;
   const int32_t* perm = nullptr;  // B_PERM of the same call
+  const int32_t* iperm = nullptr; // B_CELL_OF: row of node i is iperm[i]
   bool matches(const double* x, const int32_t* k, int64_t N_, int d_,
                int n_) const {
     return d2 && x == xyz && k == knn && N_ == N && d_ == d && n_ == n;
