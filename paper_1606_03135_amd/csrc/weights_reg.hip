@@ -57,6 +57,11 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
   __shared__ double lam_s[S + 1];  // acceptance mode: Lambda per column
   __shared__ double dif_s[3 * S];  // acceptance mode: x_q - x_k
   __shared__ int refcol_s;
+  // per-stencil uniforms parked here for the passes, so they are not held
+  // in registers (and spilled) across the elimination: the operator
+  // direction, the unscale factor, the center
+  __shared__ double sv_s[4];
+  __shared__ int ck_s;
   __shared__ unsigned long long accw_s[2];
 
   const int lane0 = threadIdx.x;
@@ -211,7 +216,13 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         acc *= v;
       }
     }
-    const double sinv = op_unscale(op, r2c, rho);
+    if (lane == 0) {
+      sv_s[0] = nrm[0];
+      sv_s[1] = nrm[1];
+      sv_s[2] = nrm[2];
+      sv_s[3] = op_unscale(op, r2c, rho);
+      ck_s = ck;
+    }
 
     for (int cb = 0; cb < ncol; cb += 8 * PL) {
       const int nb = min(8 * PL, ncol - cb);
@@ -223,10 +234,11 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
       __asm__ volatile("" : "+v"(lane));
       const int r = lane & 7, c = lane >> 3;
       wsync();
+      const double n0 = sv_s[0], n1 = sv_s[1], n2 = sv_s[2];
       for (int t = lane; t < nb * M; t += 64) {
         const int e = t / M, s = t - e * M;
         lpsi_s[t] = monomial_op_pw(pw_s + 3 * cols_s[cb + e] * l1, l1,
-                                   ex_s + 3 * s, op, nrm[0], nrm[1], nrm[2]);
+                                   ex_s + 3 * s, op, n0, n1, n2);
       }
       wsync();
       // ---- assemble [A_hat | B_hat] ----
@@ -265,7 +277,7 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
                 const double dx = pe[0] - xi0, dy = pe[1] - xi1;
                 const double dz = pe[2] - xi2;
                 v = phs_op(dx, dy, dz, dx * dx + dy * dy + dz * dz, m, d, op,
-                           nrm[0], nrm[1], nrm[2]);
+                           n0, n1, n2);
               } else {
                 v = lpsi_s[e * M + (i - n)];
               }
@@ -396,12 +408,15 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
       });
       // ---- unscale, write rows, Lebesgue values ----
       // row slot with rank j holds the unknown x_j; weights are x_j, j < n
-      if (singular && lane == 0) report(P.st, ORBF_ESINGULAR, ck);
+      const int32_t ckp = ck_s;
+      const double sinv = sv_s[3];
+      const int32_t* stnp = P.knn + (int64_t)ckp * n;
+      if (singular && lane == 0) report(P.st, ORBF_ESINGULAR, ckp);
       sfor<0, PL>([&](auto jpc) __attribute__((always_inline)) {
         constexpr int jp = decltype(jpc)::value;
         const int e = 8 * jp + c;
         const bool live = e < nb;
-        const int32_t row = live ? stn[cols_s[cb + e]] : 0;
+        const int32_t row = live ? stnp[cols_s[cb + e]] : 0;
         double lam = 0.0;
         sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
           constexpr int ii = decltype(iic)::value;
@@ -449,14 +464,14 @@ __global__ __launch_bounds__(64, 2) void weights_reg_kernel(WeightsParams P) {
         const int q = cols_s[e];
         const bool acc = q == 0 || (e < efail && lam_s[e] <= P.tau * lref);
         // only candidate positions (the covering's masks) carry a bit
-        const uint64_t word = P.ball[2 * (int64_t)ck + (q >> 6)];
+        const uint64_t word = P.ball[2 * (int64_t)ck_s + (q >> 6)];
         if (acc && q != 0 && ((word >> (q & 63)) & 1ull))
           atomicOr(&accw_s[q >> 6], 1ull << (q & 63));
       }
       wsync();
       if (lane == 0) {
-        P.accept[2 * (int64_t)ck] = accw_s[0];
-        P.accept[2 * (int64_t)ck + 1] = accw_s[1];
+        P.accept[2 * (int64_t)ck_s] = accw_s[0];
+        P.accept[2 * (int64_t)ck_s + 1] = accw_s[1];
       }
       wsync();
     }
