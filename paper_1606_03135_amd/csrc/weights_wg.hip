@@ -40,7 +40,7 @@ template <int L, int PL>
 __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
   constexpr int LC = L + PL;
   constexpr int S = kG * L;
-  extern __shared__ double dyn_s[];  // psi | L psi | powers | strip
+  extern __shared__ double dyn_s[];  // psi | L psi | powers
   __shared__ double xi_s[3 * S];
   __shared__ int cols_s[S];
   __shared__ int8_t ex_s[3 * 36];
@@ -58,7 +58,6 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
   double* psi_s = dyn_s;
   double* lpsi_s = psi_s + n * M;
   double* pw_s = lpsi_s + kG * PL * M;
-  double* strip = pw_s + 3 * n * l1;
   for (int q = t0; q < 3 * M; q += kThreads) ex_s[q] = P.ex[q];
   // eliminations write only values in [0, K) here, so with this start no
   // rank read below can index out of range
@@ -153,7 +152,9 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
                                    ex_s + 3 * s, op, nrm[0], nrm[1], nrm[2]);
       }
       __syncthreads();
-      // ---- assemble [A_hat | B_hat] through a per-thread LDS strip ----
+      // ---- assemble [A_hat | B_hat] straight into the registers ----
+      // (unrolled; a runtime loop through a per-thread LDS strip measured
+      // 10.0 against 9.65 ms for K = 140 on a 200k ball)
       double a[L][LC];
       sfor<0, L>([&](auto iic) __attribute__((always_inline)) {
         constexpr int ii = decltype(iic)::value;
@@ -162,10 +163,10 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
         const double xi0 = ri ? xi_s[3 * i] : 0.0;
         const double xi1 = ri ? xi_s[3 * i + 1] : 0.0;
         const double xi2 = ri ? xi_s[3 * i + 2] : 0.0;
-#pragma clang loop unroll(disable)
-        for (int jj = 0; jj < LC; ++jj) {
+        sfor<0, LC>([&](auto jjc) __attribute__((always_inline)) {
+          constexpr int jj = decltype(jjc)::value;
           double v = 0.0;
-          if (jj < L) {
+          if constexpr (jj < L) {
             const int j = kG * jj + c;
             if (i < n && j < n) {
               const double dx = xi0 - xi_s[3 * j], dy = xi1 - xi_s[3 * j + 1];
@@ -190,11 +191,7 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
               }
             }
           }
-          strip[jj * kThreads + t] = v;
-        }
-        sfor<0, LC>([&](auto jjc) __attribute__((always_inline)) {
-          constexpr int jj = decltype(jjc)::value;
-          a[ii][jj] = strip[jj * kThreads + t];
+          a[ii][jj] = v;
         });
       });
       // ---- partial pivoting, rows in place, Gauss-Jordan sweep ----
@@ -333,8 +330,7 @@ __global__ __launch_bounds__(256, 2) void weights_wg_kernel(WeightsParams P) {
 template <int L, int PL>
 bool launch_wg(orbf_ctx* ctx, const WeightsParams& P, int64_t work) {
   const size_t dyn = ((size_t)P.n * P.M + (size_t)kG * PL * P.M +
-                      (size_t)3 * P.n * (P.l + 1) +
-                      (size_t)(L + PL) * kThreads) * sizeof(double);
+                      (size_t)3 * P.n * (P.l + 1)) * sizeof(double);
   static bool attr_set = false;  // set once, outside any graph capture
   if (!attr_set) {
     if (hipFuncSetAttribute((const void*)weights_wg_kernel<L, PL>,
