@@ -61,7 +61,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs summarised in this file, together with the SHA-256 of the
 # kernel sources they were taken on; a stale summary reports null.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "weights_reg_ball1M_traffic.md")
-KERNEL_SOURCES = ["paper_1606_03135_amd/csrc/weights_reg.hip",
+KERNEL_SOURCES = ["paper_1606_03135_amd/csrc/weights_reg_kernel.hpp",
                   "paper_1606_03135_amd/csrc/weights_common.hpp"]
 COPY_BYTES = 1 << 30
 

@@ -10,7 +10,9 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liborbf.so")
 SOURCES = ["api.hip", "scan.hip", "knn.hip", "cover.hip", "weights.hip",
-           "weights_reg.hip", "weights_ir.hip", "weights_wg.hip", "weights_mfma.hip",
+           "weights_reg.hip", "weights_reg_3_6.hip", "weights_reg_7_8.hip",
+           "weights_reg_9.hip", "weights_ir.hip", "weights_wg.hip",
+           "weights_mfma.hip",
            "lebesgue.hip", "csr.hip", "gershgorin.hip", "krylov.hip", "ilu.hip",
            "batch.hip", "peak.hip"]
 ARCH = os.environ.get("ORBF_OFFLOAD_ARCH", "gfx950")
