@@ -22,10 +22,10 @@ namespace {
 
 constexpr int kWaves = 4;    // wavefronts per block in the query kernel
 constexpr int kKeep = 256;   // LDS capacity for ranked candidates per wave
-// consecutive (cell-ordered) queries per wave: 16 in 3D, 8 in 2D (1M-node
-// ball: 2.86 ms at 16, 2.89 at 8, 3.18 at 32; 100k-node disk: 0.293 ms at
-// 16, 0.258 at 8)
-__host__ __device__ constexpr int run_length(int d) { return d == 2 ? 8 : 16; }
+// consecutive (cell-ordered) queries per wave: 8 in 3D, 4 in 2D (with the
+// branch-free sort; 1M-node ball: 2.18 ms at 8, 2.20 at 16, 2.48 at 32;
+// 100k-node disk: 0.208 ms at 4, 0.220 at 8)
+__host__ __device__ constexpr int run_length(int d) { return d == 2 ? 4 : 8; }
 // first threshold: kGrow x the previous query's n-th squared distance; small
 // enough that about n (1 + 1.5 (kGrow - 1)) candidates pass, so most sets fit
 // one key per lane, large enough that few queries need a second pass
