@@ -43,18 +43,20 @@ __global__ __launch_bounds__(256) void row_len_kernel(
 }
 
 // Rank of every stencil position within its stencil, once per stencil.
-// A wavefront reads the owners of 64 consecutive nodes in one load and
-// ranks, one after the other, the stencils of those that own themselves
-// (centers, explicit rows); lane q takes position q (and q + 64).
+// A wavefront reads the owners of npw consecutive nodes (npw <= 64) in one
+// load and ranks, one after the other, the stencils of those that own
+// themselves (centers, explicit rows); lane q takes position q (and q + 64).
+// Each other position's index is broadcast by readlane from a uniform lane,
+// so a step is a scalar read and a compare, with no LDS round trip.
 template <int PER_LANE>
 __global__ __launch_bounds__(256) void stencil_rank_kernel(
     const int32_t* __restrict__ knn, const int32_t* __restrict__ owner,
-    int64_t N, int n, uint8_t* __restrict__ crank) {
+    int64_t N, int n, int npw, uint8_t* __restrict__ crank) {
   const int lane = threadIdx.x & 63;
-  const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+  const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * npw;
   if (e0 >= N) return;  // whole wavefront
   const int64_t me = e0 + lane;
-  unsigned long long self = __ballot(me < N && owner[me] == me);
+  unsigned long long self = __ballot(lane < npw && me < N && owner[me] == me);
   while (self) {
     const int64_t e = e0 + __ffsll((long long)self) - 1;
     self &= self - 1;
@@ -69,8 +71,18 @@ __global__ __launch_bounds__(256) void stencil_rank_kernel(
     for (int h = 0; h < PER_LANE; ++h) rank[h] = 0;
 #pragma unroll
     for (int g = 0; g < PER_LANE; ++g) {
-      for (int s = 0; s < 64; ++s) {
-        const int32_t v = __shfl(idx[g], s, 64);
+      const int lim = n - 64 * g < 64 ? n - 64 * g : 64;  // uniform
+      int s = 0;
+      for (; s + 4 <= lim; s += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t v = __builtin_amdgcn_readlane(idx[g], s + u);
+#pragma unroll
+          for (int h = 0; h < PER_LANE; ++h) rank[h] += v < idx[h];
+        }
+      }
+      for (; s < lim; ++s) {
+        const int32_t v = __builtin_amdgcn_readlane(idx[g], s);
 #pragma unroll
         for (int h = 0; h < PER_LANE; ++h) rank[h] += v < idx[h];
       }
@@ -150,14 +162,19 @@ orbf_status csr_kernels(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
   st = scan_tmp ? exclusive_scan_i32_to_i64_tmp(ctx, len, N, row_ptr, scan_tmp)
                 : exclusive_scan_i32_to_i64(ctx, len, N, row_ptr);
   if (st) return st;
-  // one wavefront per 64 nodes, four per block
-  const dim3 rgrid((unsigned)((N + 255) / 256));
+  // one wavefront per npw nodes, four per block: 64 nodes while that still
+  // gives 4096 wavefronts, fewer (down to one) for small node sets, whose
+  // stencils would otherwise be ranked by a few wavefronts in series
+  int npw = 64;
+  while (npw > 1 && (N + npw - 1) / npw < 4096) npw >>= 1;
+  const int64_t waves = (N + npw - 1) / npw;
+  const dim3 rgrid((unsigned)((waves + 3) / 4));
   if (n <= 64)
     hipLaunchKernelGGL(stencil_rank_kernel<1>, rgrid, dim3(256), 0, s, knn,
-                       owner, N, n, crank);
+                       owner, N, n, npw, crank);
   else
     hipLaunchKernelGGL(stencil_rank_kernel<2>, rgrid, dim3(256), 0, s, knn,
-                       owner, N, n, crank);
+                       owner, N, n, npw, crank);
   const int rpb = 256 / n;  // n <= 128
   const int64_t steps = (N + rpb - 1) / rpb;
   const dim3 grid((unsigned)(steps < (1 << 16) ? steps : (1 << 16)));

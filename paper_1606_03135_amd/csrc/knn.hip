@@ -24,7 +24,8 @@ constexpr int kWaves = 4;    // wavefronts per block in the query kernel
 constexpr int kKeep = 256;   // LDS capacity for ranked candidates per wave
 // consecutive (cell-ordered) queries per wave: 8 in 3D, 4 in 2D (with the
 // branch-free sort; 1M-node ball: 2.18 ms at 8, 2.20 at 16, 2.48 at 32;
-// 100k-node disk: 0.208 ms at 4, 0.220 at 8)
+// 100k-node disk: 0.208 ms at 4, 0.220 at 8); halved until the launch has
+// 4096 wavefronts, down to one query per wave for sets of under 4096 nodes
 __host__ __device__ constexpr int run_length(int d) { return d == 2 ? 4 : 8; }
 // first threshold: kGrow x the previous query's n-th squared distance; small
 // enough that about n (1 + 1.5 (kGrow - 1)) candidates pass, so most sets fit
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
     const double* __restrict__ xs, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ cstart, const GridParams* __restrict__ gpp,
-    int64_t N, int d, int n, int32_t* __restrict__ knn,
+    int64_t N, int d, int n, int run, int32_t* __restrict__ knn,
     double* __restrict__ rho2, double* __restrict__ d2,
     DevStatus* __restrict__ st) {
   __shared__ double kd[kWaves][kKeep];
@@ -358,7 +359,6 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const GridParams g = *gpp;
   double est = 0.0;  // previous query's n-th squared distance (0: none)
-  const int run = run_length(d);
   const int64_t q_begin = ((int64_t)blockIdx.x * kWaves + w) * run;
   const int64_t q_end = min(q_begin + run, N);
 
@@ -545,11 +545,14 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   if (st) return st;
   hipLaunchKernelGGL(cell_scatter_kernel, dim3(g1), dim3(256), 0, s, xyz, N, d,
                      cell_of, rank, cstart, perm, xs);
-  const int64_t per_block = (int64_t)kWaves * run_length(d);
+  // shorter runs for small node sets, so that they still fill the chip
+  int run = run_length(d);
+  while (run > 1 && (N + run - 1) / run < 4096) run >>= 1;
+  const int64_t per_block = (int64_t)kWaves * run;
   const int64_t qblocks = (N + per_block - 1) / per_block;
   hipLaunchKernelGGL(knn_query_kernel, dim3((unsigned)qblocks),
                      dim3(64 * kWaves), 0, s, xs, perm, cstart, gp, N, d, n,
-                     knn, rho2, d2, ctx->status);
+                     run, knn, rho2, d2, ctx->status);
   ctx->d2_cache = {xyz, knn, N, d, n, d2, perm, cell_of};
   return hip_check(ctx, hipGetLastError(), "knn");
 }
