@@ -163,10 +163,11 @@ orbf_status csr_kernels(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
                 : exclusive_scan_i32_to_i64(ctx, len, N, row_ptr);
   if (st) return st;
   // one wavefront per npw nodes, four per block: 64 nodes while that still
-  // gives 4096 wavefronts, fewer (down to one) for small node sets, whose
-  // stencils would otherwise be ranked by a few wavefronts in series
+  // gives 65536 wavefronts, fewer (down to one) for smaller node sets, so
+  // that each wavefront ranks few stencils in series (each one a dependent
+  // load of its indices)
   int npw = 64;
-  while (npw > 1 && (N + npw - 1) / npw < 4096) npw >>= 1;
+  while (npw > 1 && (N + npw - 1) / npw < 65536) npw >>= 1;
   const int64_t waves = (N + npw - 1) / npw;
   const dim3 rgrid((unsigned)((waves + 3) / 4));
   if (n <= 64)
