@@ -180,11 +180,15 @@ constexpr int kStack = 16;     // LDS stack entries per group
 //   follow 4 at every level         1.39 /  5.4 /  6.0; 1.72 / 5.40; 7.50e8
 //   follow 16 for 4 levels, then 1  1.09 /  3.7 /  4.1; 1.15 / 3.48; 7.99e8
 // (then 0: 1.14 / 4.3 / 4.7; then 2: 1.08 / 3.8 / 4.5; 256 or fewer blocks
-// per level: slower on deep DAGs).
+// per level: slower on deep DAGs; all at up to 1024 blocks per level).
 constexpr int kFollowWide = 16;  // nodes followed per entry, first levels
 constexpr int kFollowDeep = 1;   // nodes followed per entry, later levels
 constexpr int kWideLevels = 4;
-constexpr int kLevelBlocks = 1024;
+// blocks per level: one per 64 nodes, at most 4096 (1M-node ball, covering
+// phase: 0.90 ms at 1024 blocks, 0.834 at 3906, 0.840 at 7813, 0.846 at
+// 15625; 2,025-node square, graph replay of a build: 168 us at 8 blocks,
+// 158 at 16, 155 at 32)
+constexpr int kLevelBlocks = 4096;
 constexpr int32_t kCenterBit = INT32_MIN;  // stack/queue entry: center flag
 
 // Seeds: eligible nodes without predecessors are centers (level 0 queue);
@@ -420,7 +424,7 @@ orbf_status run_levels(orbf_ctx* ctx, hipStream_t s, const CoverSet& one,
                        int32_t* q0, int32_t* q1, int32_t* qc, int64_t N,
                        const void* key_ptr) {
   orbf_status st = ORBF_OK;
-  const int64_t want_blocks = (N + 255) / 256;
+  const int64_t want_blocks = (N + 63) / 64;
   const unsigned gl =
       (unsigned)(want_blocks < kLevelBlocks ? want_blocks : kLevelBlocks);
   int lv = 0;
