@@ -167,17 +167,23 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
+// The dimension is a template argument, so the axis loop unrolls and each
+// thread keeps several grid-stride steps' loads in flight.
+template <int D>
 __global__ __launch_bounds__(256) void bbox_partial_kernel(
-    const double* __restrict__ x, int64_t N, int d, double* __restrict__ part,
+    const double* __restrict__ x, int64_t N, double* __restrict__ part,
     DevStatus* __restrict__ st) {
   __shared__ double s[6][256];
   bool bad = false;
   double mn[3] = {INFINITY, INFINITY, INFINITY};
   double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  const int64_t stride = (int64_t)gridDim.x * 256;
+#pragma unroll 4
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * 256) {
-    for (int a = 0; a < d; ++a) {
-      double v = x[i * d + a];
+       i += stride) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double v = x[i * D + a];
       bad |= !isfinite(v);
       mn[a] = fmin(mn[a], v);
       mx[a] = fmax(mx[a], v);
@@ -533,8 +539,12 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   const double alpha = 0.9;  // cell side in units of the mean stencil radius
   hipStream_t s = ctx->stream;
   const unsigned g1 = (unsigned)((N + 255) / 256);
-  hipLaunchKernelGGL(bbox_partial_kernel, dim3(nblk), dim3(256), 0, s, xyz, N,
-                     d, part, ctx->status);
+  if (d == 2)
+    hipLaunchKernelGGL(bbox_partial_kernel<2>, dim3(nblk), dim3(256), 0, s,
+                       xyz, N, part, ctx->status);
+  else
+    hipLaunchKernelGGL(bbox_partial_kernel<3>, dim3(nblk), dim3(256), 0, s,
+                       xyz, N, part, ctx->status);
   hipLaunchKernelGGL(grid_params_kernel, dim3(1), dim3(256), 0, s, part, nblk,
                      N, d, n, cap, alpha, gp, ctx->status);
   hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((cap + 256) / 256)),
