@@ -54,6 +54,11 @@ CASES = {
     "square45_d02": dict(kind="square", n=12, m=3, l=2, delta=0.2),
     "disk5k_d05": dict(kind="disk", N=5000, n=31, m=5, l=4, delta=0.5),
     "ball20k_d03": dict(kind="ball", N=20000, n=50, m=5, l=3, delta=0.3),
+    # prefix sums over N items at the edge of the one-block scan (16384
+    # items: four full chunks) and just past it (tile scans, then the
+    # one-block scan of the 17 tile sums)
+    "ball16384_d03": dict(kind="ball", N=16384, n=20, m=3, l=2, delta=0.3),
+    "ball16385_d03": dict(kind="ball", N=16385, n=20, m=3, l=2, delta=0.3),
     # spatially sorted nodes: the covering's dependency DAG is deep
     "ball20k_lex_d03": dict(kind="ball_lex", N=20000, n=50, m=5, l=3,
                             delta=0.3),
