@@ -249,19 +249,23 @@ __device__ __forceinline__ void lfollow_entry(
   }
 }
 
-// One propagation-only level: the entries of `list` (count *count), one
-// group of sixteen lanes each; *zero (the count the previous level read) is
-// cleared for the next.
+// One propagation-only level, number `lvl`: the entries of `list` (count
+// *count), one group of sixteen lanes each; *zero (the count the previous
+// level read) is cleared for the next, and a level with entries records
+// its number in *depth.
 __global__ __launch_bounds__(256) void lfollow_kernel(
     const int32_t* __restrict__ list, const int64_t* __restrict__ count,
     const int32_t* __restrict__ knn, int n, const uint64_t* __restrict__ ball,
     const uint64_t* __restrict__ acc, int32_t* open, int32_t* state,
     int32_t* owner, int32_t* next, int64_t* next_count, int64_t* zero,
-    int follow) {
+    int follow, int64_t lvl, int64_t* depth) {
   __shared__ int32_t stk[16 * kLStack];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *zero = 0;
   const int grp = threadIdx.x >> 4;
   const int64_t cnt = *count;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *zero = 0;
+    if (cnt > 0) *depth = lvl;
+  }
   for (int64_t t = (int64_t)blockIdx.x * 16 + grp; t < cnt;
        t += (int64_t)gridDim.x * 16)
     lfollow_entry(list[t], stk + grp * kLStack, knn, n, ball, acc, open,
@@ -292,8 +296,9 @@ __global__ __launch_bounds__(256) void lcompact_kernel(
   if (j < N && flag[j]) list[pos[j]] = (int32_t)j;
 }
 
-__global__ void lzero3_kernel(int64_t* c) {
-  if (threadIdx.x < 3) c[threadIdx.x] = 0;
+// the three list counts and the last propagation level with entries
+__global__ void lzero4_kernel(int64_t* c) {
+  if (threadIdx.x < 4) c[threadIdx.x] = 0;
 }
 
 __global__ void lzero1_kernel(int64_t* c) {
@@ -334,7 +339,7 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
   hipLaunchKernelGGL(lzero_kernel, dim3(gz), dim3(256), 0, s, open, N + 1);
   // acceptance words need no clearing: a center's are written by its solve
   // before its propagation reads them, and nothing else reads them
-  hipLaunchKernelGGL(lzero3_kernel, dim3(1), dim3(64), 0, s, cnt);
+  hipLaunchKernelGGL(lzero4_kernel, dim3(1), dim3(64), 0, s, cnt);
   launch_ball(ctx, P0.xyz, P0.knn, P0.rho2, N, d, n, t2, eligible, ball, open,
               state, L_UNDECIDED, L_INELIGIBLE);
   hipLaunchKernelGGL(lseed_kernel, dim3(g), dim3(256), 0, s, open, N, state,
@@ -372,7 +377,14 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
     return ORBF_OK;
   };
   // The solved levels run back to back and the host checks once after
-  // them; the propagation-only levels after batches of 1, 2, 4, ... 64.
+  // them; the propagation-only levels after batches of 1, 2, 4, ... 64, or
+  // first after as many as the last call on the same arrays needed.
+  const std::pair<const void*, int64_t> key(P0.knn, N);
+  int64_t recorded = 0;
+  for (size_t i = 0; i < ctx->leb_keys.size(); ++i)
+    if (ctx->leb_keys[i] == key) recorded = ctx->leb_levels[i];
+  int64_t first_prop = -1;  // number of the first propagation-only level
+  bool from_record = false;  // the current batch is the recorded depth
   int batch = (int)kSolvedLevels;
   for (;;) {
     for (int r = 0; r < batch; ++r, ++level) {
@@ -385,15 +397,35 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
       } else {
         hipLaunchKernelGGL(lfollow_kernel, dim3(gf), dim3(256), 0, s, list[a],
                            cnt + a, P0.knn, n, ball, acc, open, state, owner,
-                           list[b], cnt + b, cnt + z, kFollow);
+                           list[b], cnt + b, cnt + z, kFollow, level, cnt + 3);
       }
     }
-    int64_t next = 0;
-    hipError_t e = hipMemcpyAsync(&next, cnt + (int)(level % 3), sizeof next,
+    int64_t counts[4] = {0, 0, 0, 0};  // list counts, last level with entries
+    hipError_t e = hipMemcpyAsync(counts, cnt, sizeof counts,
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if ((st = hip_check(ctx, e, "Lebesgue covering level"))) return st;
-    if (next == 0) break;
+    if (counts[level % 3] == 0) {
+      if (first_prop >= 0) {
+        const int64_t need =
+            counts[3] >= first_prop ? counts[3] - first_prop + 1 : 0;
+        bool found = false;
+        for (size_t i = 0; i < ctx->leb_keys.size(); ++i)
+          if (ctx->leb_keys[i] == key) {
+            ctx->leb_levels[i] = need;
+            found = true;
+          }
+        if (!found) {
+          if (ctx->leb_keys.size() >= 4096) {
+            ctx->leb_keys.clear();
+            ctx->leb_levels.clear();
+          }
+          ctx->leb_keys.push_back(key);
+          ctx->leb_levels.push_back(need);
+        }
+      }
+      break;
+    }
     if (level > N + 2)
       return fail(ctx, ORBF_EINTERNAL, "Lebesgue covering did not settle");
     if (solving) {
@@ -407,10 +439,16 @@ orbf_status launch_lebesgue_cover(orbf_ctx* ctx, const WeightsParams& P0,
       if ((st = solve(list[z], cnt + z))) return st;
       hipLaunchKernelGGL(lzero1_kernel, dim3(1), dim3(64), 0, s, cnt + z);
       solving = false;
-      batch = 1;
+      first_prop = level;
+      // the recorded depth plus two (a group that follows its own decisions
+      // can move the depth by a level or so between calls); if that falls
+      // short, the doubling starts again from one
+      from_record = recorded > 0 && recorded < N;
+      batch = from_record ? (int)recorded + 2 : 1;
       continue;
     }
-    batch = batch < 64 ? 2 * batch : 64;
+    batch = from_record ? 1 : batch < 64 ? 2 * batch : 64;
+    from_record = false;
   }
   hipLaunchKernelGGL(lfinal_kernel, dim3(g), dim3(256), 0, s, state, N, owner,
                      flag, ctx->status);

@@ -149,6 +149,10 @@ struct orbf_ctx {
   // needed in an eager call; a captured call replays that many
   std::vector<std::pair<const void*, int64_t>> cover_keys;
   std::vector<int> cover_rounds;
+  // propagation-only levels the Lebesgue covering of each (knn, N) needed;
+  // a repeated call launches that many before its first read-back
+  std::vector<std::pair<const void*, int64_t>> leb_keys;
+  std::vector<int64_t> leb_levels;
   // weights kernel schedules: rows of (K, pclass, orbf_schedule)
   std::vector<int> schedules;
   int ir_max_corrections = 8;  // FP32 + refinement: cap before FP64 fallback
