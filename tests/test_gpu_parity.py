@@ -204,6 +204,45 @@ def test_disk_full_size(orbf, ctx, order):
     assert err <= TOL
 
 
+def test_lebesgue_recorded_depth_other_inputs(orbf, ctx):
+    """The Lebesgue covering keeps the depth of its propagation-only levels
+    per (knn buffer, N) and starts a repeated call with that many levels.
+    Three 20k-node disk sets of one size alternate on one context, each
+    result freed before the next call so the caching allocator hands the
+    same buffers back: two Poisson-disk generation orders (deep DAGs of
+    different depth, delta 0.5 and 0.2) and a shuffled one (shallow, no
+    propagation-only levels).  Each call starts from another set's depth,
+    short or long, and must still give the oracle's covering."""
+    specs = {"gen05": ("generation", 0.5), "gen02": ("generation", 0.2),
+             "shuf05": ("shuffled", 0.5)}
+    data, refs = {}, {}
+    for key, (order, delta) in specs.items():
+        D = nodesets.disk(20000, 200, 1, order=order)
+        data[key] = D
+        refs[key] = oracle.build_dm(D["x"], 31, 5, 4, delta, tau=5.0,
+                                    eligible=D["eligible"])
+        assert refs[key]["min_margin"] > 1e-9
+    for key in ("gen05", "gen02", "gen05", "shuf05", "gen02", "gen05",
+                "gen05"):
+        D, ref = data[key], refs[key]
+        _say(f"[gpu] Lebesgue recorded depth: {key}")
+        got = orbf.build_dm(gpu(D["x"]), 31, 5, 4, specs[key][1], tau=5.0,
+                            eligible=gpu(D["eligible"]), ctx=ctx)
+        owner = got["owner"].cpu().numpy()
+        assert np.array_equal(owner, ref["owner"])
+        nc = int(got["n_centers"].item())
+        assert np.array_equal(got["centers"].cpu().numpy()[:nc],
+                              ref["centers"])
+        # no boundary rows here: nnz = row_ptr[N] of the N * n slots
+        row_ptr = got["row_ptr"].cpu().numpy()
+        assert np.array_equal(row_ptr, ref["row_ptr"])
+        assert np.array_equal(got["col"].cpu().numpy()[:row_ptr[-1]],
+                              ref["col"])
+        rows = owner >= 0
+        assert row_err(got["W"].cpu().numpy()[rows], ref["W"][rows]) <= TOL
+        del got
+
+
 def _morton(x, bits=10):
     """Morton (Z-order) permutation of points in [-1, 1]^3."""
     q = np.clip(((x + 1) / 2 * (1 << bits)).astype(np.int64), 0,
