@@ -68,11 +68,10 @@ __global__ __launch_bounds__(256) void ball_kernel(
 // Retention balls from the squared distances the kNN recorded for the same
 // arrays (identical values: same formula, same operand order): one
 // wavefront per node, taken in node order so the masks, states, stencil
-// rows and radii stream (the distance row of node c, 8 n contiguous bytes,
-// is row iperm[c] of the kNN's cell order); lane q tests stencil position q
-// and a ballot forms the mask.
+// rows, distance rows (the kNN writes them in node order) and radii
+// stream; lane q tests stencil position q and a ballot forms the mask.
 __global__ __launch_bounds__(256) void ball_d2_kernel(
-    const double* __restrict__ d2s, const int32_t* __restrict__ iperm,
+    const double* __restrict__ d2s,
     const int32_t* __restrict__ knn, const double* __restrict__ rho2,
     int64_t N, int n, double t2, const uint8_t* __restrict__ eligible,
     uint64_t* __restrict__ ball, int32_t* __restrict__ indeg,
@@ -80,7 +79,7 @@ __global__ __launch_bounds__(256) void ball_d2_kernel(
   const int64_t c = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (c >= N) return;  // whole wavefront
-  const double* d2 = d2s + (int64_t)iperm[c] * n;
+  const double* d2 = d2s + c * n;
   const bool ec = eligible == nullptr || eligible[c] != 0;
   const double thr = t2 * rho2[c];
   uint64_t b[2] = {0ull, 0ull};
@@ -108,7 +107,7 @@ __global__ __launch_bounds__(256) void ball_d2_kernel(
 // node and four stencil positions per lane: each wavefront has four nodes'
 // dependent loads and all their in-degree updates in flight at once.
 __global__ __launch_bounds__(256) void ball_d2_quad_kernel(
-    const double* __restrict__ d2s, const int32_t* __restrict__ iperm,
+    const double* __restrict__ d2s,
     const int32_t* __restrict__ knn, const double* __restrict__ rho2,
     int64_t N, int n, double t2, const uint8_t* __restrict__ eligible,
     uint64_t* __restrict__ ball, int32_t* __restrict__ indeg,
@@ -116,11 +115,9 @@ __global__ __launch_bounds__(256) void ball_d2_quad_kernel(
   const int lane = threadIdx.x & 63, part = lane >> 4, pl = lane & 15;
   const int64_t c = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 6) * 4 + part;
   const bool valid = c < N;  // no early return: the ballots need every lane
-  int64_t qs = 0;
   bool ec = false;
   double thr = 0.0;
   if (valid) {
-    qs = iperm[c];
     ec = eligible == nullptr || eligible[c] != 0;
     thr = t2 * rho2[c];
   }
@@ -130,7 +127,7 @@ __global__ __launch_bounds__(256) void ball_d2_quad_kernel(
     const int q = pl + 16 * i;
     bool in = false;
     if (ec && q >= 1 && q < n) {
-      const double dq = d2s[qs * n + q];
+      const double dq = d2s[c * n + q];
       const int32_t j = knn[c * n + q];
       if (j > c && j < N && (eligible == nullptr || eligible[j] != 0) &&
           dq <= thr) {
@@ -393,12 +390,12 @@ void launch_ball(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   hipStream_t s = ctx->stream;
   if (ctx->d2_cache.matches(xyz, knn, N, d, n) && n <= 64) {
     hipLaunchKernelGGL(ball_d2_quad_kernel, dim3((unsigned)((N + 15) / 16)),
-                       dim3(256), 0, s, ctx->d2_cache.d2, ctx->d2_cache.iperm,
+                       dim3(256), 0, s, ctx->d2_cache.d2,
                        knn, rho2, N, n, t2, eligible, ball, indeg, state,
                        s_open, s_inel);
   } else if (ctx->d2_cache.matches(xyz, knn, N, d, n)) {
     hipLaunchKernelGGL(ball_d2_kernel, dim3((unsigned)((N + 3) / 4)),
-                       dim3(256), 0, s, ctx->d2_cache.d2, ctx->d2_cache.iperm,
+                       dim3(256), 0, s, ctx->d2_cache.d2,
                        knn, rho2, N, n, t2, eligible, ball, indeg, state,
                        s_open, s_inel);
   } else {

@@ -324,18 +324,15 @@ __global__ __launch_bounds__(256) void cell_count_kernel(
   }
 }
 
-// Also turns cell_of into the inverse permutation: cell_of[i] = position
-// of node i in cell order (each thread reads and then overwrites its own).
 __global__ __launch_bounds__(256) void cell_scatter_kernel(
     const double* __restrict__ x, int64_t N, int d,
-    int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank,
+    const int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank,
     const int64_t* __restrict__ start, int32_t* __restrict__ perm,
     double* __restrict__ xs) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * 256) {
     int64_t pos = start[cell_of[i]] + rank[i];
     perm[pos] = (int32_t)i;
-    cell_of[i] = (int32_t)pos;
     for (int a = 0; a < d; ++a) xs[pos * d + a] = x[i * d + a];
   }
 }
@@ -472,10 +469,10 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
           est = (base <= 64)
                     ? rank_sorted<1>(kd[w], kj[w], base, n, lane,
                                      knn + (int64_t)qi * n,
-                                     d2 + qs * n, rho2 + qi)
+                                     d2 + (int64_t)qi * n, rho2 + qi)
                     : rank_sorted<2>(kd[w], kj[w], base, n, lane,
                                      knn + (int64_t)qi * n,
-                                     d2 + qs * n, rho2 + qi);
+                                     d2 + (int64_t)qi * n, rho2 + qi);
           wave_sync();
           done = true;
           break;
@@ -491,7 +488,7 @@ __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
           }
           if (r < n) {
             knn[(int64_t)qi * n + r] = jt;
-            d2[qs * n + r] = dt;
+            d2[(int64_t)qi * n + r] = dt;
             if (r == n - 1) {
               rho2[qi] = dt;
               kth[w] = dt;  // n-th distance, the next query's first guess
@@ -533,7 +530,8 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   auto* perm = (int32_t*)scratch(ctx, B_PERM, (size_t)N * 4, &st);
   auto* xs = (double*)scratch(ctx, B_XS, (size_t)N * d * 8, &st);
   // squared distance of every stencil member, kept for the covering, in
-  // cell order (row qs belongs to node perm[qs]): contiguous writes
+  // node order like knn (row i: node i's stencil), so that the covering
+  // reads it as a stream
   auto* d2 = (double*)scratch(ctx, B_KNN_D2, (size_t)N * n * 8, &st);
   if (st) return st;
   const double alpha = 0.9;  // cell side in units of the mean stencil radius
@@ -563,7 +561,7 @@ orbf_status launch_knn(orbf_ctx* ctx, const double* xyz, int64_t N, int d,
   hipLaunchKernelGGL(knn_query_kernel, dim3((unsigned)qblocks),
                      dim3(64 * kWaves), 0, s, xs, perm, cstart, gp, N, d, n,
                      run, knn, rho2, d2, ctx->status);
-  ctx->d2_cache = {xyz, knn, N, d, n, d2, perm, cell_of};
+  ctx->d2_cache = {xyz, knn, N, d, n, d2};
   return hip_check(ctx, hipGetLastError(), "knn");
 }
 

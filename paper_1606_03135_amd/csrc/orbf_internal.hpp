@@ -65,9 +65,7 @@ struct D2Cache {
   const int32_t* knn = nullptr;
   int64_t N = 0;
   int d = 0, n = 0;
-  const double* d2 = nullptr;
-  const int32_t* perm = nullptr;  // B_PERM of the same call
-  const int32_t* iperm = nullptr; // B_CELL_OF: row of node i is iperm[i]
+  const double* d2 = nullptr;  // row i: squared distances of node i's stencil
   bool matches(const double* x, const int32_t* k, int64_t N_, int d_,
                int n_) const {
     return d2 && x == xyz && k == knn && N_ == N && d_ == d && n_ == n;
