@@ -43,7 +43,10 @@ namespace {
 
 constexpr int64_t kSolveGrid = 4096;  // accept-mode solve blocks per level
 constexpr unsigned kPropBlocks = 256;   // propagation: 4 wavefronts a block
-constexpr int64_t kSolvedLevels = 4;    // levels solved one by one
+// levels solved one by one before the speculative solve (100k disk, whole
+// build, shuffled / generation order: 1.52 / 4.08-4.14 ms at 3, 1.555 /
+// 4.10 at 4, 1.474 / 4.09-4.16 at 6, 1.49 / 4.09-4.11 at 8)
+constexpr int64_t kSolvedLevels = 6;
 // propagation-only levels: 16 groups a block (100k disk in generation
 // order, whole build: 4.02-4.06 ms at 128, 512 and 2048 blocks alike; the
 // levels are launch bound)
