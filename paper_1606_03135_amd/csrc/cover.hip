@@ -190,27 +190,43 @@ constexpr int32_t kCenterBit = INT32_MIN;  // stack/queue entry: center flag
 
 // Seeds: eligible nodes without predecessors are centers (level 0 queue);
 // owner and is_center are initialised for every node.
-__global__ __launch_bounds__(256) void seed_kernel(
+constexpr int kSeedThreads = 1024;
+
+// One queue reservation per block: the seeds of all sixteen wavefronts are
+// counted in LDS and appended with a single atomic (one per wavefront had
+// 15.6k atomics on one counter for 1M nodes).
+__global__ __launch_bounds__(kSeedThreads) void seed_kernel(
     const int32_t* __restrict__ cnt, int64_t N, int32_t* state,
     int32_t* __restrict__ owner, int32_t* __restrict__ is_center,
     int32_t* __restrict__ q, int32_t* qn, int64_t base) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
-  const bool open = state[j] == S_UNDECIDED;
-  const bool seed = open && cnt[j] == 0;
-  owner[j] = seed ? (int32_t)j : open ? INT32_MAX : -1;
-  is_center[j] = seed;
-  if (seed) {
-    state[j] = S_CENTER;
-    const uint64_t m = __ballot(true);  // the seeding lanes of this wave
-    const int lane = (int)(threadIdx.x & 63);
-    const int leader = __ffsll((long long)m) - 1;
-    int at = 0;
-    if (lane == leader) at = atomicAdd(qn, (int)__popcll(m));
-    at = __shfl(at, leader, 64);
-    q[at + (int)__popcll(m & ((1ull << lane) - 1))] =
-        (int32_t)(j + base) | kCenterBit;
+  __shared__ int wcount[kSeedThreads / 64];
+  __shared__ int wbase[kSeedThreads / 64];
+  const int64_t j = (int64_t)blockIdx.x * kSeedThreads + threadIdx.x;
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  bool seed = false;  // no early return: the block synchronises below
+  if (j < N) {
+    const bool open = state[j] == S_UNDECIDED;
+    seed = open && cnt[j] == 0;
+    owner[j] = seed ? (int32_t)j : open ? INT32_MAX : -1;
+    is_center[j] = seed;
+    if (seed) state[j] = S_CENTER;
   }
+  const uint64_t m = __ballot(seed);  // the seeding lanes of this wave
+  if (lane == 0) wcount[w] = (int)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int v = 0; v < kSeedThreads / 64; ++v) tot += wcount[v];
+    int at = tot ? atomicAdd(qn, tot) : 0;
+    for (int v = 0; v < kSeedThreads / 64; ++v) {
+      wbase[v] = at;
+      at += wcount[v];
+    }
+  }
+  __syncthreads();
+  if (seed)
+    q[wbase[w] + (int)__popcll(m & ((1ull << lane) - 1))] =
+        (int32_t)(j + base) | kCenterBit;
 }
 
 // Process one queue entry (and what the group follows) with the sixteen
@@ -519,14 +535,14 @@ orbf_status launch_cover(orbf_ctx* ctx, const double* xyz, const int32_t* knn,
   auto* qc = (int32_t*)scratch(ctx, B_MISC2, 64, &st);
   if (st) return st;
   hipStream_t s = ctx->stream;
-  const unsigned g = (unsigned)((N + 255) / 256);
   const unsigned gz = (unsigned)((N + 256) / 256 < 65535 ? (N + 256) / 256 : 65535);
   hipLaunchKernelGGL(zero_i32_kernel, dim3(gz), dim3(256), 0, s, cnt, N + 1);
   hipLaunchKernelGGL(zero3_i32_kernel, dim3(1), dim3(64), 0, s, qc);
   launch_ball(ctx, xyz, knn, rho2, N, d, n, t2, eligible, ball, cnt, state,
               S_UNDECIDED, S_INELIGIBLE);
-  hipLaunchKernelGGL(seed_kernel, dim3(g), dim3(256), 0, s, cnt, N, state,
-                     owner, flag, q0, qc, (int64_t)0);
+  const unsigned gs = (unsigned)((N + kSeedThreads - 1) / kSeedThreads);
+  hipLaunchKernelGGL(seed_kernel, dim3(gs), dim3(kSeedThreads), 0, s, cnt, N,
+                     state, owner, flag, q0, qc, (int64_t)0);
   const CoverSet one{knn, owner, 0, n};
   st = run_levels(ctx, s, one, nullptr, nullptr, ball, cnt, flag, q0, q1, qc,
                   N, knn);
@@ -550,9 +566,10 @@ orbf_status cover_multi_prologue(orbf_ctx* w, const double* xyz,
                      mc.setid + base, N, set_index);
   launch_ball(w, xyz, knn, rho2, N, d, n, t2, eligible, mc.ball + 2 * base,
               mc.cnt + base, mc.state + base, S_UNDECIDED, S_INELIGIBLE);
-  hipLaunchKernelGGL(seed_kernel, dim3(g), dim3(256), 0, s, mc.cnt + base, N,
-                     mc.state + base, owner, mc.flag + base, mc.q0, mc.qc,
-                     base);
+  const unsigned gs = (unsigned)((N + kSeedThreads - 1) / kSeedThreads);
+  hipLaunchKernelGGL(seed_kernel, dim3(gs), dim3(kSeedThreads), 0, s,
+                     mc.cnt + base, N, mc.state + base, owner, mc.flag + base,
+                     mc.q0, mc.qc, base);
   return hip_check(w, hipGetLastError(), "batched cover prologue");
 }
 
