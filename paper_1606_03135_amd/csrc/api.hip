@@ -148,7 +148,11 @@ orbf_status orbf_create(int device, void* hip_stream, size_t hbm_budget_bytes,
       hipHostMalloc((void**)&ctx->host_counter, sizeof(int64_t),
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&ctx->host_scalars, 128 * sizeof(double),
-                    hipHostMallocDefault) != hipSuccess) {
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->cover_extra_host, sizeof(int64_t),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->cover_ev, hipEventDisableTiming) !=
+          hipSuccess) {
     delete ctx;
     return ORBF_ENOMEM;
   }
@@ -179,6 +183,8 @@ void orbf_destroy(orbf_ctx* ctx) {
   if (ctx->status_host) hipHostFree(ctx->status_host);
   if (ctx->host_counter) hipHostFree(ctx->host_counter);
   if (ctx->host_scalars) hipHostFree(ctx->host_scalars);
+  if (ctx->cover_extra_host) hipHostFree(ctx->cover_extra_host);
+  if (ctx->cover_ev) hipEventDestroy(ctx->cover_ev);
   if (ctx->cover_tab_host) hipHostFree(ctx->cover_tab_host);
   for (auto& e : ctx->ev)
     if (e) hipEventDestroy(e);

@@ -330,16 +330,19 @@ __global__ __launch_bounds__(256) void level_kernel(
 
 // One workgroup runs the remaining levels from `lv` until a queue is empty.
 // Every node enters a queue at most once, so at most N + 1 levels remain.
+// The number of levels it ran goes to *ran (if not null).
 template <bool MULTI>
 __global__ __launch_bounds__(256) void finish_levels_kernel(
     CoverSet one, const CoverSet* __restrict__ tab,
     const int32_t* __restrict__ setid, const uint64_t* __restrict__ ball,
     int64_t N, int32_t* cnt, int32_t* __restrict__ is_center,
-    int32_t* __restrict__ q0, int32_t* __restrict__ q1, int32_t* qc, int lv) {
+    int32_t* __restrict__ q0, int32_t* __restrict__ q1, int32_t* qc, int lv,
+    int32_t* ran) {
   __shared__ int32_t stk[16 * kStack];
   __shared__ int32_t count;
   const int grp = threadIdx.x >> 4;
-  for (int64_t k = 0; k <= N; ++k, ++lv) {
+  int64_t k = 0;
+  for (; k <= N; ++k, ++lv) {
     __syncthreads();
     if (threadIdx.x == 0) {
       count = __atomic_load_n(&qc[lv % 3], __ATOMIC_RELAXED);
@@ -355,6 +358,7 @@ __global__ __launch_bounds__(256) void finish_levels_kernel(
                            kFollowDeep);
     __threadfence();
   }
+  if (ran && threadIdx.x == 0) *ran = (int32_t)(k < INT32_MAX ? k : INT32_MAX);
 }
 
 __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t n,
@@ -460,8 +464,39 @@ orbf_status run_levels(orbf_ctx* ctx, hipStream_t s, const CoverSet& one,
   int recorded = -1;
   for (size_t i = 0; i < ctx->cover_keys.size(); ++i)
     if (ctx->cover_keys[i] == key) recorded = ctx->cover_rounds[i];
+  // an earlier replay's report, if it has arrived: the levels its
+  // finishing workgroup still ran are added to that key's count
+  if (ctx->cover_pending && cap == hipStreamCaptureStatusNone &&
+      hipEventQuery(ctx->cover_ev) == hipSuccess) {
+    const int extra = *ctx->cover_extra_host;
+    for (size_t i = 0; i < ctx->cover_keys.size(); ++i)
+      if (ctx->cover_keys[i] == ctx->cover_pending_key && extra > 0)
+        ctx->cover_rounds[i] =
+            ctx->cover_rounds[i] + extra < kMaxLevels
+                ? ctx->cover_rounds[i] + extra
+                : kMaxLevels;
+    ctx->cover_pending = false;
+    for (size_t i = 0; i < ctx->cover_keys.size(); ++i)
+      if (ctx->cover_keys[i] == key) recorded = ctx->cover_rounds[i];
+  }
   if (cap != hipStreamCaptureStatusNone) {
     levels(recorded > 0 ? recorded : kFirstLevels);
+  } else if (recorded > 0 && !tab) {
+    // a repeated eager call: the recorded count and the finishing
+    // workgroup, as a captured call runs them, with no read-back; the
+    // workgroup's level count comes back asynchronously
+    levels(recorded);
+    int32_t* ran = qc + 3;
+    hipLaunchKernelGGL(finish_levels_kernel<false>, dim3(1), dim3(256), 0, s,
+                       one, tab, setid, ball, N, cnt, flag, q0, q1, qc, lv,
+                       ran);
+    hipError_t e = hipMemcpyAsync(ctx->cover_extra_host, ran, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(ctx->cover_ev, s);
+    if ((st = hip_check(ctx, e, "cover: level report"))) return st;
+    ctx->cover_pending = true;
+    ctx->cover_pending_key = key;
+    return hip_check(ctx, hipGetLastError(), "cover levels");
   } else {
     // a repeated call on the same arrays starts with the recorded count
     int batch = recorded > 0 ? recorded : kFirstLevels;
@@ -491,10 +526,12 @@ orbf_status run_levels(orbf_ctx* ctx, hipStream_t s, const CoverSet& one,
   }
   if (tab)
     hipLaunchKernelGGL(finish_levels_kernel<true>, dim3(1), dim3(256), 0, s,
-                       one, tab, setid, ball, N, cnt, flag, q0, q1, qc, lv);
+                       one, tab, setid, ball, N, cnt, flag, q0, q1, qc, lv,
+                       (int32_t*)nullptr);
   else
     hipLaunchKernelGGL(finish_levels_kernel<false>, dim3(1), dim3(256), 0, s,
-                       one, tab, setid, ball, N, cnt, flag, q0, q1, qc, lv);
+                       one, tab, setid, ball, N, cnt, flag, q0, q1, qc, lv,
+                       (int32_t*)nullptr);
   return hip_check(ctx, hipGetLastError(), "cover levels");
 }
 

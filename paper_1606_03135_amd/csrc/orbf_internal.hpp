@@ -147,6 +147,14 @@ struct orbf_ctx {
   // needed in an eager call; a captured call replays that many
   std::vector<std::pair<const void*, int64_t>> cover_keys;
   std::vector<int> cover_rounds;
+  // an eager covering that replayed its recorded count without a read-back
+  // leaves the number of levels its finishing workgroup still ran in
+  // cover_extra_host (pinned) once cover_ev has completed; a later call
+  // adds it to the count of cover_pending_key
+  hipEvent_t cover_ev = nullptr;
+  int32_t* cover_extra_host = nullptr;
+  bool cover_pending = false;
+  std::pair<const void*, int64_t> cover_pending_key{nullptr, 0};
   // propagation-only levels the Lebesgue covering of each (knn, N) needed;
   // a repeated call launches that many before its first read-back
   std::vector<std::pair<const void*, int64_t>> leb_keys;

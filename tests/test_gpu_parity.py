@@ -204,6 +204,33 @@ def test_disk_full_size(orbf, ctx, order):
     assert err <= TOL
 
 
+def test_cover_recorded_levels_other_inputs(orbf, ctx):
+    """A repeated eager covering on the same (knn buffer, N) launches the
+    recorded number of levels and lets one workgroup finish whatever is
+    left, with no read-back; the workgroup's level count raises the record
+    asynchronously.  A shallow DAG (20k-node Halton ball) and a deep one
+    (the same nodes in lexicographic order) alternate on one context, each
+    result freed before the next call so the same buffers come back: a
+    deep call can start from the shallow set's count.  Every call must
+    give the oracle's covering."""
+    x = nodesets.ball(20000, 2)["x"]
+    sets = {"halton": x,
+            "lex": np.ascontiguousarray(
+                x[np.lexsort((x[:, 2], x[:, 1], x[:, 0]))])}
+    refs = {k: oracle.build_dm(v, 20, 3, 2, 0.3) for k, v in sets.items()}
+    for key in ("halton", "halton", "lex", "halton", "lex", "lex", "lex"):
+        _say(f"[gpu] cover recorded levels: {key}")
+        got = orbf.build_dm(gpu(sets[key]), 20, 3, 2, 0.3, ctx=ctx)
+        ref = refs[key]
+        assert np.array_equal(got["owner"].cpu().numpy(), ref["owner"])
+        nc = int(got["n_centers"].item())
+        assert np.array_equal(got["centers"].cpu().numpy()[:nc],
+                              ref["centers"])
+        assert np.array_equal(got["row_ptr"].cpu().numpy(), ref["row_ptr"])
+        assert np.array_equal(got["col"].cpu().numpy(), ref["col"])
+        del got
+
+
 def test_lebesgue_recorded_depth_other_inputs(orbf, ctx):
     """The Lebesgue covering keeps the depth of its propagation-only levels
     per (knn buffer, N) and starts a repeated call with that many levels.
