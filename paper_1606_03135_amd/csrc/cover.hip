@@ -178,6 +178,11 @@ constexpr int kStack = 16;     // LDS stack entries per group
 //   follow 16 for 4 levels, then 1  1.09 /  3.7 /  4.1; 1.15 / 3.48; 7.99e8
 // (then 0: 1.14 / 4.3 / 4.7; then 2: 1.08 / 3.8 / 4.5; 256 or fewer blocks
 // per level: slower on deep DAGs; all at up to 1024 blocks per level).
+// Retaken at up to 4096 blocks, covering in ms, 1M-node Halton ball /
+// lexicographic ball / 200k and 20k rasters: built 0.78 / 3.98 / 4.06 /
+// 1.32; follow 32 first 0.76 / 4.10 / 4.11 / 1.41; follow 8 first 1.00 /
+// 3.93 / 4.07 / 1.32; 2 wide levels 0.79 / 3.91 / 4.08 / 1.33; 8 wide
+// levels 0.78 / 4.13 / 4.11 / 1.41.
 constexpr int kFollowWide = 16;  // nodes followed per entry, first levels
 constexpr int kFollowDeep = 1;   // nodes followed per entry, later levels
 constexpr int kWideLevels = 4;
