@@ -169,6 +169,12 @@ __global__ __launch_bounds__(256) void ball_d2_quad_kernel(
 // scattered numbering); on the deep, narrow DAGs of spatially ordered
 // inputs it only serialises atomics, so later levels follow one.
 constexpr int kStack = 16;     // LDS stack entries per group
+// queue pushes a level block stages in LDS and appends with one atomic
+// (one per group and push put tens of thousands of atomics on one counter
+// in the first levels of a 1M-node set); pushes past it go straight to
+// the queue
+constexpr int kLStage = 1024;
+constexpr int32_t kStageMin = 2048;  // levels with fewer entries do not stage
 // Measured, covering phase in ms: 1M-node ball in Halton / Morton /
 // lexicographic order; 2D raster grids of 20k and 200k nodes at delta 0.3;
 // the 512-set batch in FP64 weights/s:
@@ -245,7 +251,7 @@ __device__ __forceinline__ void process_entry(
     const CoverSet* __restrict__ tab, const int32_t* __restrict__ setid,
     const uint64_t* __restrict__ ball, int32_t* cnt,
     int32_t* __restrict__ is_center, int32_t* __restrict__ qnext, int32_t* qn,
-    int follow) {
+    int follow, int32_t* lq = nullptr, int32_t* lqn = nullptr) {
   const int lane = (int)(threadIdx.x & 63), pl = lane & 15;
   const int gshift = lane & 48;  // first lane of the group in the wave
   const uint32_t below = (1u << pl) - 1u;
@@ -289,13 +295,36 @@ __device__ __forceinline__ void process_entry(
       const int keep = k < room ? k : room;
       const int r = __popc(m & below);
       int base = 0;
+      int staged = 0;  // the pushes go to the block's LDS stage
       if (k > keep) {
-        if (pl == __ffs(m) - 1) base = atomicAdd(qn, k - keep);
+        const int np = k - keep;
+        if (pl == __ffs(m) - 1) {
+          // reserve np stage slots (compare-and-swap: a reservation is
+          // all or nothing, so the stage has no holes); else the queue
+          int at = -1;
+          if (lq) {
+            int old = __hip_atomic_load(lqn, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+            while (old + np <= kLStage) {
+              const int prev = atomicCAS(lqn, old, old + np);
+              if (prev == old) {
+                at = old;
+                break;
+              }
+              old = prev;
+            }
+          }
+          staged = at >= 0;
+          base = staged ? at : atomicAdd(qn, np);
+        }
         base = __shfl(base, gshift + __ffs(m) - 1, 64);
+        staged = __shfl(staged, gshift + __ffs(m) - 1, 64);
       }
       if (dec[i] != -1) {
         if (r < keep)
           stk[sp + r] = dec[i];
+        else if (staged)
+          lq[base + r - keep] = dec[i];
         else
           qnext[base + r - keep] = dec[i];
       }
@@ -321,16 +350,33 @@ __global__ __launch_bounds__(256) void level_kernel(
     int32_t* cnt, int32_t* __restrict__ is_center, int32_t* __restrict__ q0,
     int32_t* __restrict__ q1, int32_t* qc, int lv, int follow) {
   __shared__ int32_t stk[16 * kStack];
+  __shared__ int32_t lq[kLStage];  // pushes staged for one queue reservation
+  __shared__ int32_t lqn, lbase;
   const int32_t count = qc[lv % 3];
   if (blockIdx.x == 0 && threadIdx.x == 0) qc[(lv + 2) % 3] = 0;
   const int32_t* cur = (lv & 1) ? q1 : q0;
   int32_t* nxt = (lv & 1) ? q0 : q1;
   int32_t* qn = &qc[(lv + 1) % 3];
   const int grp = threadIdx.x >> 4;
+  // narrow levels push little and pay only the barriers: no stage there
+  // (the choice is the same for every block)
+  const bool stage = count >= kStageMin;
+  if (stage) {
+    if (threadIdx.x == 0) lqn = 0;
+    __syncthreads();
+  }
   for (int64_t t = (int64_t)blockIdx.x * 16 + grp; t < count;
        t += (int64_t)gridDim.x * 16)
     process_entry<MULTI>(cur[t], stk + grp * kStack, one, tab, setid, ball,
-                         cnt, is_center, nxt, qn, follow);
+                         cnt, is_center, nxt, qn, follow,
+                         stage ? lq : nullptr, stage ? &lqn : nullptr);
+  if (stage) {
+    __syncthreads();
+    const int staged = lqn;
+    if (threadIdx.x == 0) lbase = staged ? atomicAdd(qn, staged) : 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < staged; t += 256) nxt[lbase + t] = lq[t];
+  }
 }
 
 // One workgroup runs the remaining levels from `lv` until a queue is empty.
