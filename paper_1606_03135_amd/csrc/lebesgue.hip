@@ -115,19 +115,39 @@ __device__ __forceinline__ void claim(int32_t c, int32_t j,
 }
 
 // owners start unset (eligible) or -1; nodes with no predecessor are the
+// push j for every lane with `take`, one atomic per wavefront (one per
+// node put up to N atomics on one counter); every lane of the wavefront
+// calls it
+__device__ __forceinline__ void push_wave(int32_t* list, int64_t* count,
+                                          int32_t j, bool take) {
+  const uint64_t m = __ballot(take);
+  if (m == 0) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((long long)m) - 1;
+  int64_t base = 0;
+  if (lane == leader)
+    base = __hip_atomic_fetch_add(count, (int64_t)__popcll(m),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = __shfl(base, leader, 64);
+  if (take)
+    __hip_atomic_store(&list[base + __popcll(m & ((1ull << lane) - 1ull))],
+                       j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // first level's centers
 __global__ __launch_bounds__(256) void lseed_kernel(
     const int32_t* __restrict__ open, int64_t N, int32_t* state,
     int32_t* __restrict__ owner, int32_t* __restrict__ list,
     int64_t* __restrict__ count) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
-  const bool el = state[j] != L_INELIGIBLE;
-  owner[j] = el ? INT32_MAX : -1;
-  if (el && open[j] == 0) {
-    state[j] = L_CENTER;
-    push(list, count, (int32_t)j);
+  bool take = false;  // no early return: the push is per wavefront
+  if (j < N) {
+    const bool el = state[j] != L_INELIGIBLE;
+    owner[j] = el ? INT32_MAX : -1;
+    take = el && open[j] == 0;
+    if (take) state[j] = L_CENTER;
   }
+  push_wave(list, count, (int32_t)j, take);
 }
 
 // every undecided node with a nonempty ball, for the speculative solve
@@ -136,10 +156,9 @@ __global__ __launch_bounds__(256) void lspec_kernel(
     const uint64_t* __restrict__ ball, int64_t N, int32_t* __restrict__ list,
     int64_t* __restrict__ count) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
-  if (state[j] == L_UNDECIDED && owner[j] == INT32_MAX &&
-      (ball[2 * j] | ball[2 * j + 1]))
-    push(list, count, (int32_t)j);
+  const bool take = j < N && state[j] == L_UNDECIDED &&
+                    owner[j] == INT32_MAX && (ball[2 * j] | ball[2 * j + 1]);
+  push_wave(list, count, (int32_t)j, take);
 }
 
 // one wavefront per center of the level; lane q takes stencil position q
