@@ -20,7 +20,9 @@ namespace orbf {
 
 namespace {
 
-constexpr int kWaves = 4;    // wavefronts per block in the query kernel
+// wavefronts per block in the query kernel (1M-node ball, kNN phase:
+// 2.058-2.063 ms at 1, 2.085-2.094 at 2, 2.135-2.145 at 4, 2.44 at 8)
+constexpr int kWaves = 1;
 constexpr int kKeep = 256;   // LDS capacity for ranked candidates per wave
 // consecutive (cell-ordered) queries per wave: 8 in 3D, 4 in 2D (with the
 // branch-free sort; 1M-node ball: 2.18 ms at 8, 2.20 at 16, 2.48 at 32;
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(256) void cell_scatter_kernel(
 // than n or more than 128 candidates.  T never exceeds the squared distance
 // to the boundary of the scanned block, so the result is exact: every node
 // outside the block is farther than every kept one.
-__global__ __launch_bounds__(256)
+__global__ __launch_bounds__(64 * kWaves)
 __attribute__((amdgpu_waves_per_eu(5))) void knn_query_kernel(
     const double* __restrict__ xs, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ cstart, const GridParams* __restrict__ gpp,
