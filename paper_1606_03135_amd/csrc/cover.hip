@@ -173,7 +173,12 @@ constexpr int kStack = 16;     // LDS stack entries per group
 // (one per group and push put tens of thousands of atomics on one counter
 // in the first levels of a 1M-node set); pushes past it go straight to
 // the queue
-constexpr int kLStage = 1024;
+// threads of a level block (covering in ms, 1M-node Halton ball /
+// lexicographic ball / 200k raster: 0.71 / 3.01 / 4.05 at 256, 0.72 /
+// 3.71 / 4.11 at 64)
+constexpr int kLevelThreads = 256;
+constexpr int kLevelGroups = kLevelThreads / 16;
+constexpr int kLStage = 4 * kLevelThreads;
 constexpr int32_t kStageMin = 2048;  // levels with fewer entries do not stage
 // Measured, covering phase in ms: 1M-node ball in Halton / Morton /
 // lexicographic order; 2D raster grids of 20k and 200k nodes at delta 0.3;
@@ -344,12 +349,12 @@ __device__ __forceinline__ void process_entry(
 // queue (count qc[(lv+1) % 3]); qc[(lv+2) % 3], read by the previous level,
 // is cleared for the next.
 template <bool MULTI>
-__global__ __launch_bounds__(256) void level_kernel(
+__global__ __launch_bounds__(kLevelThreads) void level_kernel(
     CoverSet one, const CoverSet* __restrict__ tab,
     const int32_t* __restrict__ setid, const uint64_t* __restrict__ ball,
     int32_t* cnt, int32_t* __restrict__ is_center, int32_t* __restrict__ q0,
     int32_t* __restrict__ q1, int32_t* qc, int lv, int follow) {
-  __shared__ int32_t stk[16 * kStack];
+  __shared__ int32_t stk[kLevelGroups * kStack];
   __shared__ int32_t lq[kLStage];  // pushes staged for one queue reservation
   __shared__ int32_t lqn, lbase;
   const int32_t count = qc[lv % 3];
@@ -365,8 +370,8 @@ __global__ __launch_bounds__(256) void level_kernel(
     if (threadIdx.x == 0) lqn = 0;
     __syncthreads();
   }
-  for (int64_t t = (int64_t)blockIdx.x * 16 + grp; t < count;
-       t += (int64_t)gridDim.x * 16)
+  for (int64_t t = (int64_t)blockIdx.x * kLevelGroups + grp; t < count;
+       t += (int64_t)gridDim.x * kLevelGroups)
     process_entry<MULTI>(cur[t], stk + grp * kStack, one, tab, setid, ball,
                          cnt, is_center, nxt, qn, follow,
                          stage ? lq : nullptr, stage ? &lqn : nullptr);
@@ -375,7 +380,8 @@ __global__ __launch_bounds__(256) void level_kernel(
     const int staged = lqn;
     if (threadIdx.x == 0) lbase = staged ? atomicAdd(qn, staged) : 0;
     __syncthreads();
-    for (int t = threadIdx.x; t < staged; t += 256) nxt[lbase + t] = lq[t];
+    for (int t = threadIdx.x; t < staged; t += kLevelThreads)
+      nxt[lbase + t] = lq[t];
   }
 }
 
@@ -492,21 +498,24 @@ orbf_status run_levels(orbf_ctx* ctx, hipStream_t s, const CoverSet& one,
                        int32_t* q0, int32_t* q1, int32_t* qc, int64_t N,
                        const void* key_ptr) {
   orbf_status st = ORBF_OK;
-  const int64_t want_blocks = (N + 63) / 64;
-  const unsigned gl =
-      (unsigned)(want_blocks < kLevelBlocks ? want_blocks : kLevelBlocks);
+  // one group of sixteen lanes per four nodes, at most 16 kLevelBlocks
+  const int64_t want_groups = (N + 3) / 4;
+  const int64_t groups =
+      want_groups < 16 * (int64_t)kLevelBlocks ? want_groups
+                                               : 16 * (int64_t)kLevelBlocks;
+  const unsigned gl = (unsigned)((groups + kLevelGroups - 1) / kLevelGroups);
   int lv = 0;
   auto levels = [&](int k) {
     for (int r = 0; r < k; ++r, ++lv) {
       const int follow = lv < kWideLevels ? kFollowWide : kFollowDeep;
       if (tab)
-        hipLaunchKernelGGL(level_kernel<true>, dim3(gl), dim3(256), 0, s, one,
-                           tab, setid, ball, cnt, flag, q0, q1, qc, lv,
-                           follow);
+        hipLaunchKernelGGL(level_kernel<true>, dim3(gl), dim3(kLevelThreads),
+                           0, s, one, tab, setid, ball, cnt, flag, q0, q1, qc,
+                           lv, follow);
       else
-        hipLaunchKernelGGL(level_kernel<false>, dim3(gl), dim3(256), 0, s,
-                           one, tab, setid, ball, cnt, flag, q0, q1, qc, lv,
-                           follow);
+        hipLaunchKernelGGL(level_kernel<false>, dim3(gl), dim3(kLevelThreads),
+                           0, s, one, tab, setid, ball, cnt, flag, q0, q1, qc,
+                           lv, follow);
     }
   };
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
