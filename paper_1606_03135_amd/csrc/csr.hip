@@ -48,12 +48,18 @@ __global__ __launch_bounds__(256) void row_len_kernel(
 // themselves (centers, explicit rows); lane q takes position q (and q + 64).
 // Each other position's index is broadcast by readlane from a uniform lane,
 // so a step is a scalar read and a compare, with no LDS round trip.
+// threads of a rank block: one wavefront, so a wavefront with many
+// centers holds no others' slots (1M-node ball, CSR phase: 0.363-0.364 ms
+// against 0.370 at 256)
+constexpr int kRankThreads = 64;
+
 template <int PER_LANE>
-__global__ __launch_bounds__(256) void stencil_rank_kernel(
+__global__ __launch_bounds__(kRankThreads) void stencil_rank_kernel(
     const int32_t* __restrict__ knn, const int32_t* __restrict__ owner,
     int64_t N, int n, int npw, uint8_t* __restrict__ crank) {
   const int lane = threadIdx.x & 63;
-  const int64_t e0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * npw;
+  const int64_t e0 =
+      ((int64_t)blockIdx.x * (kRankThreads / 64) + (threadIdx.x >> 6)) * npw;
   if (e0 >= N) return;  // whole wavefront
   const int64_t me = e0 + lane;
   unsigned long long self = __ballot(lane < npw && me < N && owner[me] == me);
@@ -162,20 +168,21 @@ orbf_status csr_kernels(orbf_ctx* ctx, int64_t N, int n, const int32_t* knn,
   st = scan_tmp ? exclusive_scan_i32_to_i64_tmp(ctx, len, N, row_ptr, scan_tmp)
                 : exclusive_scan_i32_to_i64(ctx, len, N, row_ptr);
   if (st) return st;
-  // one wavefront per npw nodes, four per block: 64 nodes while that still
+  // one wavefront per npw nodes: 64 nodes while that still
   // gives 65536 wavefronts, fewer (down to one) for smaller node sets, so
   // that each wavefront ranks few stencils in series (each one a dependent
   // load of its indices)
   int npw = 64;
   while (npw > 1 && (N + npw - 1) / npw < 65536) npw >>= 1;
   const int64_t waves = (N + npw - 1) / npw;
-  const dim3 rgrid((unsigned)((waves + 3) / 4));
+  constexpr int wpb = kRankThreads / 64;
+  const dim3 rgrid((unsigned)((waves + wpb - 1) / wpb));
   if (n <= 64)
-    hipLaunchKernelGGL(stencil_rank_kernel<1>, rgrid, dim3(256), 0, s, knn,
-                       owner, N, n, npw, crank);
+    hipLaunchKernelGGL(stencil_rank_kernel<1>, rgrid, dim3(kRankThreads), 0,
+                       s, knn, owner, N, n, npw, crank);
   else
-    hipLaunchKernelGGL(stencil_rank_kernel<2>, rgrid, dim3(256), 0, s, knn,
-                       owner, N, n, npw, crank);
+    hipLaunchKernelGGL(stencil_rank_kernel<2>, rgrid, dim3(kRankThreads), 0,
+                       s, knn, owner, N, n, npw, crank);
   const int rpb = 256 / n;  // n <= 128
   const int64_t steps = (N + rpb - 1) / rpb;
   const dim3 grid((unsigned)(steps < (1 << 16) ? steps : (1 << 16)));
