@@ -21,7 +21,9 @@ namespace orbf {
 namespace {
 
 // wavefronts per block in the query kernel (1M-node ball, kNN phase:
-// 2.058-2.063 ms at 1, 2.085-2.094 at 2, 2.135-2.145 at 4, 2.44 at 8)
+// 2.058-2.063 ms at 1, 2.085-2.094 at 2, 2.135-2.145 at 4, 2.44 at 8; at
+// one per block, 2.048 ms with five wavefronts per SIMD, 2.30 with four,
+// 2.107 with six)
 constexpr int kWaves = 1;
 constexpr int kKeep = 256;   // LDS capacity for ranked candidates per wave
 // consecutive (cell-ordered) queries per wave: 8 in 3D, 4 in 2D (with the
