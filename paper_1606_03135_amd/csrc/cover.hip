@@ -121,14 +121,25 @@ __global__ __launch_bounds__(256) void ball_d2_quad_kernel(
     ec = eligible == nullptr || eligible[c] != 0;
     thr = t2 * rho2[c];
   }
+  // the row loads do not wait for the node's own eligibility (they are in
+  // bounds for every valid node), so both round trips overlap
+  double dq4[4];
+  int32_t j4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = pl + 16 * i;
+    const bool ld = valid && q >= 1 && q < n;
+    dq4[i] = ld ? d2s[c * n + q] : 0.0;
+    j4[i] = ld ? knn[c * n + q] : -1;
+  }
   uint64_t bw[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int q = pl + 16 * i;
     bool in = false;
     if (ec && q >= 1 && q < n) {
-      const double dq = d2s[c * n + q];
-      const int32_t j = knn[c * n + q];
+      const double dq = dq4[i];
+      const int32_t j = j4[i];
       if (j > c && j < N && (eligible == nullptr || eligible[j] != 0) &&
           dq <= thr) {
         in = true;
